@@ -1,0 +1,292 @@
+/*
+ * arrow.h -- C ABI of the MI355X (gfx950) arrow-decomposition SpMM library.
+ *
+ * The library computes the iterated sparse x tall-skinny dense product
+ *
+ *     Y_t = A X_t,   X_{t+1} = Y_t / ||Y_t||_col            (t = 0 .. T-1)
+ *
+ * (problem statement of Section 2, "Matrices": X_{t+1} = sigma(A X_t) with
+ * sigma a per-column normalisation) over an arrow matrix decomposition
+ *
+ *     A = sum_i P_{pi_i} B_i P_{pi_i}^T                       (Section 3, Eq. (1))
+ *
+ * where every B_i has arrow width b: its nonzeros lie in the first b rows, the
+ * first b columns, or the band |p - q| <= b (Section 1, 0-based here).
+ *
+ * Two stages:
+ *   1. arrow_decompose (host, C++): LA-Decompose of Section 4.1 with the
+ *      random spanning forest linear arrangement of Section 4.3 and the
+ *      smallest-first tree order of Section 4.4.
+ *   2. arrow_plan_create uploads the decomposition to one GPU; arrow_spmm /
+ *      arrow_spmm_iterate run the product with hand-written HIP kernels.
+ *
+ * Conventions for every function:
+ *   - Return value: ARROW_OK (0) or an error code; arrow_last_error() gives a
+ *     thread-local description of the last failure.  On failure, out-handles
+ *     are set to NULL and nothing is leaked.
+ *   - Argument errors are detected synchronously before any device work.
+ *   - "device" pointers are HIP device memory of the plan's GPU and belong to
+ *     the caller; the library never frees them.  "host" pointers are ordinary
+ *     CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued asynchronously on it; faults in that work
+ *     surface at the caller's next synchronisation.
+ *   - Dense matrices are row-major with a row stride (`ld`, in elements).
+ *     Row and column storage must be 16-byte aligned: the base pointer and
+ *     ld * element_size must be multiples of 16.
+ *   - Feature width k must be a positive multiple of 16.
+ *   - Decompositions and plans are immutable after creation; concurrent calls
+ *     on one plan from several streams are safe when each call has its own
+ *     workspace and outputs.
+ */
+#ifndef ARROW_H
+#define ARROW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t arrow_status_t;
+enum {
+    ARROW_OK = 0,
+    ARROW_ERR_INVALID_ARG = 1,   /* bad argument: null pointer, bad CSR, bad size */
+    ARROW_ERR_OUT_OF_MEMORY = 2, /* host or device allocation failed */
+    ARROW_ERR_HIP = 3,           /* a HIP runtime call failed */
+    ARROW_ERR_UNSUPPORTED = 4,   /* valid but not supported (e.g. too many levels) */
+    ARROW_ERR_IO = 5,            /* file error or corrupt file in save/load */
+    ARROW_ERR_INTERNAL = 6
+};
+
+/* Storage type of X and Y.  Products are always accumulated in FP32. */
+typedef int32_t arrow_dtype_t;
+enum {
+    ARROW_F32 = 0,
+    ARROW_F16 = 1,     /* IEEE binary16, per-column power-of-two scale */
+    ARROW_BF16 = 2,    /* bfloat16, no scale needed (scale pointer may be NULL) */
+    ARROW_F8E4M3 = 3   /* OCP FP8 E4M3FN (max 448), per-column power-of-two scale */
+};
+
+/* Linear arrangement used for the non-head vertices of each level. */
+typedef int32_t arrow_la_t;
+enum {
+    ARROW_LA_RANDOM_FOREST = 0, /* random spanning forest + smallest-first order (Sections 4.3-4.4) */
+    ARROW_LA_IDENTITY = 1       /* vertices in id order (the input's own ordering) */
+};
+
+typedef struct arrow_decomp_s *arrow_decomp_t; /* host object */
+typedef struct arrow_plan_s *arrow_plan_t;     /* device-resident object */
+
+/* ------------------------------------------------------------------------ */
+/* Stage 1: decomposition (host)                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t b;          /* arrow width, >= 2 (Section 4.1 requires b >= 2) */
+    arrow_la_t la;      /* linear arrangement kind */
+    uint64_t seed;      /* seed of the random edge weights (Section 4.3, step 1) */
+    int32_t max_levels; /* 0 = unlimited; otherwise fail with ARROW_ERR_UNSUPPORTED above it */
+    int32_t reserved;
+} arrow_decompose_opts_t;
+
+/*
+ * LA-Decompose (Section 4.1) of the square n x n CSR matrix (host arrays):
+ * row_ptr int64[n+1], col int32[nnz] strictly increasing within each row and
+ * < n, val float32[nnz]; nnz < 2^31.  The pattern is symmetrised for the graph
+ * steps (degrees, spanning forest); every stored entry keeps its own value and
+ * lands in exactly one level.  Level 0 spans all n positions; later levels are
+ * compacted to the positions that hold entries (Section 3, "collect the
+ * non-zeros at the top").  The result depends only on the inputs and opts.
+ * Errors: ARROW_ERR_INVALID_ARG for a malformed CSR or b < 2.
+ */
+arrow_status_t arrow_decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                               const float *val, const arrow_decompose_opts_t *opts,
+                               arrow_decomp_t *out);
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t b, levels;
+    double seconds;       /* wall time of arrow_decompose */
+} arrow_decomp_info_t;
+
+arrow_status_t arrow_decomp_info(arrow_decomp_t d, arrow_decomp_info_t *out);
+
+/*
+ * Export level `level` (host pointers owned by the decomposition, valid until
+ * arrow_decomp_destroy): n_i positions, vertex_of_pos int32[n_i] (the vertex
+ * placed at each position, i.e. pi_i^{-1} restricted to [0, n_i)), and B_i as
+ * CSR over positions: row_ptr int64[n_i+1], col int32[nnz_i], val float32[nnz_i].
+ */
+arrow_status_t arrow_decomp_level(arrow_decomp_t d, int32_t level, int64_t *n_i,
+                                  int64_t *nnz_i, const int32_t **vertex_of_pos,
+                                  const int64_t **row_ptr, const int32_t **col,
+                                  const float **val);
+
+/* Versioned binary file with a checksum; load rejects corrupt files (ARROW_ERR_IO). */
+arrow_status_t arrow_decomp_save(arrow_decomp_t d, const char *path);
+arrow_status_t arrow_decomp_load(const char *path, arrow_decomp_t *out);
+void arrow_decomp_destroy(arrow_decomp_t d);
+
+/* ------------------------------------------------------------------------ */
+/* Stage 2: device plan and products                                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Upload a decomposition to GPU `device` as a plan (the arrow tiles of
+ * Section 3.1 become row blocks of work; the level maps pi_i become
+ * precomputed gather indices into the level-0 order).  Synchronous: returns
+ * after the upload finished.  The plan does not reference `d` afterwards.
+ */
+arrow_status_t arrow_plan_create(arrow_decomp_t d, int32_t device, void *stream,
+                                 arrow_plan_t *out);
+void arrow_plan_destroy(arrow_plan_t p);
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t b, levels;
+    int64_t footprint_bytes;  /* device memory owned by the plan */
+    int64_t chunked_rows;     /* rows split into nnz chunks (the head rows and long rows) */
+    int64_t chunks;           /* number of chunks */
+    int64_t upper_rows;       /* rows of levels >= 1 that hold entries */
+    int64_t contributions;    /* summands gathered by the level-0 pass */
+    double a_inf_norm;        /* max_i sum_j |A_ij| (bounds the FP8/FP16 scales) */
+} arrow_plan_info_t;
+
+arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);
+
+/* Kernel ids for arrow_plan_kernel_bytes and the profiling counters. */
+enum {
+    ARROW_KERNEL_CHUNKS = 0,  /* head rows and long rows, nnz-balanced chunks */
+    ARROW_KERNEL_UPPER = 1,   /* rows of levels >= 1 (gathered through pi_0 o pi_i^{-1}) */
+    ARROW_KERNEL_LEVEL0 = 2,  /* level-0 band + head columns + cross-level sum + store */
+    ARROW_KERNEL_NORM = 3,    /* FP64 column norms and next scales */
+    ARROW_KERNEL_PERMUTE = 4, /* permute in / out */
+    ARROW_KERNEL_COUNT = 5
+};
+
+/*
+ * Algorithmic HBM bytes one launch of `kernel` moves for one product with k
+ * columns of `dtype` (every matrix entry, index and X/Y/partial row counted
+ * once), written to *bytes.  Used for the roofline.
+ */
+arrow_status_t arrow_plan_kernel_bytes(arrow_plan_t p, int32_t kernel, int64_t k,
+                                       arrow_dtype_t dtype, int64_t *bytes);
+
+/* Device workspace bytes needed by arrow_spmm for one operand of k columns
+ * (arrow_spmm_iterate needs arrow_iterate_workspace_size instead). */
+arrow_status_t arrow_workspace_size(arrow_plan_t p, int64_t k, arrow_dtype_t dtype,
+                                    size_t *bytes);
+
+/*
+ * X_plan = P_{pi_0}^T X: row p of x_plan receives row pi_0^{-1}(p) of the
+ * original-order FP32 input x (device, ldx >= k), converted to `dtype`.
+ * For ARROW_F16 / ARROW_F8E4M3 the per-column power-of-two scale s_j (so that
+ * max_i |x_ij| / s_j fits the format) is computed and written to
+ * x_scale (device float[k], required for those types, ignored otherwise);
+ * x_maxabs (device float[k] or NULL) receives max_i |code_ij| per column.
+ */
+arrow_status_t arrow_permute_in(arrow_plan_t p, const float *x, int64_t ldx, void *x_plan,
+                                int64_t ld, arrow_dtype_t dtype, int64_t k, float *x_scale,
+                                float *x_maxabs, void *stream);
+
+/*
+ * y = P_{pi_0} Y_plan, dequantised to FP32: row pi_0^{-1}(p) of y (device,
+ * ldy >= k) receives row p of y_plan times x_scale[j] (NULL = 1) times
+ * col_factor[j] (device double[k], NULL = 1).
+ */
+arrow_status_t arrow_permute_out(arrow_plan_t p, const void *y_plan, int64_t ld,
+                                 arrow_dtype_t dtype, int64_t k, const float *x_scale,
+                                 const double *col_factor, float *y, int64_t ldy, void *stream);
+
+/*
+ * One operand of a product: a column block of one request, in plan order.
+ * Y[:, j] = x_scale[j] * x_inv_norm[j] * (A Q)[:, j] where Q is x as stored;
+ * the linearity of the product folds the previous step's normalisation into
+ * this one, so no separate scaling pass over X is needed.
+ */
+typedef struct {
+    const void *x;            /* device, n rows, stride ldx elements */
+    void *y;                  /* device, n rows, stride ldy elements; must not alias x */
+    int64_t k;                /* columns, multiple of 16 */
+    int64_t ldx, ldy;
+    arrow_dtype_t dtype;      /* storage type of both x and y */
+    int32_t reserved;
+    const float *x_scale;     /* device float[k]: x = x_scale * code; NULL = 1 */
+    const double *x_inv_norm; /* device double[k]: factor of this product; NULL = 1 */
+    const float *x_maxabs;    /* device float[k]: max |code| of x (F16/F8); NULL = format max */
+    float *y_scale;           /* device float[k] out: scale y is stored with (required F16/F8) */
+    float *y_maxabs;          /* device float[k] out: max |code| of y, or NULL */
+    double *y_norm;           /* device double[k] out: ||Y[:, j]||_2 of the stored y, or NULL */
+    double *y_inv_norm;       /* device double[k] out: 1/||Y[:, j]||_2 (0 for a zero column), or NULL */
+} arrow_operand_t;
+
+/*
+ * One product Y = A X for each operand, enqueued on `stream`.  Column norms
+ * are computed in FP64 with a fixed reduction order, so every operand's
+ * result is bitwise independent of the other operands in the call.
+ * `workspace` (device) must hold arrow_workspace_size bytes per operand
+ * (the sum over operands).
+ */
+arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t num_ops,
+                          void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace for arrow_spmm_iterate (product buffers plus the ping-pong state). */
+arrow_status_t arrow_iterate_workspace_size(arrow_plan_t p, int64_t k, arrow_dtype_t dtype,
+                                            size_t *bytes);
+
+enum { ARROW_ITER_RENORM = 1 };
+
+/*
+ * `iters` products of the iteration.  x (device, plan order, stride ld) holds
+ * X_0 and is not modified; y (device, stride ld) receives the last product
+ * Y_{T-1} un-normalised; intermediate products live in the workspace.
+ * With ARROW_ITER_RENORM the input of step t >= 1 is Y_{t-1}/||Y_{t-1}||_col,
+ * otherwise Y_{t-1} itself.  norms (device double[iters*k] or NULL) receives
+ * ||Y_t[:, j]||_2 at [t*k + j].  For F16/F8 x_scale (device float[k]) is the
+ * scale of x and y_scale (device float[k], required) receives the scale of y.
+ */
+arrow_status_t arrow_spmm_iterate(arrow_plan_t p, const void *x, void *y, int64_t k, int64_t ld,
+                                  arrow_dtype_t dtype, const float *x_scale, float *y_scale,
+                                  int32_t iters, uint32_t flags, double *norms,
+                                  void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Baselines, calibration and measurement                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Plain CSR SpMM on the device, the comparison baseline: y = A x with the
+ * CSR (device row_ptr int32[n+1], col int32[nnz], val float32[nnz]) in
+ * whatever order the caller uploaded, FP32 x/y (stride ld), plus the same
+ * FP64 column-norm epilogue when sumsq_ws (device double workspace of
+ * arrow_csr_workspace_size bytes) and norms (device double[k]) are non-NULL.
+ */
+arrow_status_t arrow_csr_workspace_size(int64_t n, int64_t k, size_t *bytes);
+arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                              const float *val, const float *x, float *y, int64_t k, int64_t ld,
+                              double *sumsq_ws, double *norms, void *stream);
+
+/* Streaming copy of `bytes` (multiple of 16) from src to dst: HBM calibration. */
+arrow_status_t arrow_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
+/*
+ * Per-kernel timing with HIP events around every launch the plan makes on
+ * the stream it is launched on.  enable = 1 starts recording (clears the
+ * totals), 0 stops.  Query returns the launch count and the summed event time
+ * in milliseconds of one kernel id (synchronises the recorded events).
+ */
+arrow_status_t arrow_profile_enable(arrow_plan_t p, int32_t enable);
+arrow_status_t arrow_profile_query(arrow_plan_t p, int32_t kernel, int64_t *launches,
+                                   double *total_ms);
+
+const char *arrow_status_string(arrow_status_t s);
+const char *arrow_last_error(void);
+/* Library version, e.g. "1.0.0". */
+const char *arrow_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARROW_H */

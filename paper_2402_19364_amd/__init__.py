@@ -1,0 +1,371 @@
+"""Python binding of libarrow: the arrow-decomposition SpMM for MI355X (gfx950).
+
+Argument marshalling only: every step runs in the C++ host code or the HIP
+kernels of ``libarrow.so``.  PyTorch supplies device memory and streams.
+
+Paper: Gianinazzi et al., "Arrow Matrix Decomposition: A Novel Approach for
+Communication-Efficient Sparse Matrix Multiplication", PPoPP 2024.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libarrow.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_IO, ERR_INTERNAL = range(7)
+F32, F16, BF16, F8E4M3 = 0, 1, 2, 3
+LA_RANDOM_FOREST, LA_IDENTITY = 0, 1
+KERNEL_CHUNKS, KERNEL_UPPER, KERNEL_LEVEL0, KERNEL_NORM, KERNEL_PERMUTE = range(5)
+KERNEL_NAMES = {KERNEL_CHUNKS: "chunks", KERNEL_UPPER: "upper", KERNEL_LEVEL0: "level0",
+                KERNEL_NORM: "norm", KERNEL_PERMUTE: "permute"}
+ITER_RENORM = 1
+
+DTYPES = {"f32": F32, "f16": F16, "bf16": BF16, "f8e4m3": F8E4M3}
+ELEM_SIZE = {F32: 4, F16: 2, BF16: 2, F8E4M3: 1}
+
+
+class ArrowError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libarrow.so is not built ({LIB_PATH}); run "
+                          "`python -m paper_2402_19364_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t)
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "arrow_decompose": [I64, P, P, P, P, pp],
+        "arrow_decomp_info": [P, P],
+        "arrow_decomp_level": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), pp, pp, pp, pp],
+        "arrow_decomp_save": [P, ctypes.c_char_p],
+        "arrow_decomp_load": [ctypes.c_char_p, pp],
+        "arrow_plan_create": [P, I32, P, pp],
+        "arrow_plan_info": [P, P],
+        "arrow_plan_kernel_bytes": [P, I32, I64, I32, ctypes.POINTER(I64)],
+        "arrow_workspace_size": [P, I64, I32, ctypes.POINTER(SZ)],
+        "arrow_iterate_workspace_size": [P, I64, I32, ctypes.POINTER(SZ)],
+        "arrow_permute_in": [P, P, I64, P, I64, I32, I64, P, P, P],
+        "arrow_permute_out": [P, P, I64, I32, I64, P, P, P, I64, P],
+        "arrow_spmm": [P, P, I32, P, SZ, P],
+        "arrow_spmm_iterate": [P, P, P, I64, I64, I32, P, P, I32, U32, P, P, SZ, P],
+        "arrow_csr_workspace_size": [I64, I64, ctypes.POINTER(SZ)],
+        "arrow_csr_spmm": [I64, P, P, P, P, P, I64, I64, P, P, P],
+        "arrow_copy": [P, P, I64, P],
+        "arrow_profile_enable": [P, I32],
+        "arrow_profile_query": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = I32
+    lib.arrow_decomp_destroy.argtypes = [P]
+    lib.arrow_decomp_destroy.restype = None
+    lib.arrow_plan_destroy.argtypes = [P]
+    lib.arrow_plan_destroy.restype = None
+    for name in ("arrow_status_string",):
+        getattr(lib, name).argtypes = [I32]
+        getattr(lib, name).restype = ctypes.c_char_p
+    lib.arrow_last_error.argtypes = []
+    lib.arrow_last_error.restype = ctypes.c_char_p
+    lib.arrow_version.argtypes = []
+    lib.arrow_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def _check(status: int):
+    if status != OK:
+        msg = _load().arrow_last_error().decode(errors="replace")
+        raise ArrowError(status, msg)
+
+
+class _DecompOpts(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int32), ("la", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("max_levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _DecompInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("b", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("b", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("footprint_bytes", ctypes.c_int64),
+                ("chunked_rows", ctypes.c_int64), ("chunks", ctypes.c_int64),
+                ("upper_rows", ctypes.c_int64), ("contributions", ctypes.c_int64),
+                ("a_inf_norm", ctypes.c_double)]
+
+
+class Operand(ctypes.Structure):
+    """arrow_operand_t: one column block of one request (device pointers)."""
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("k", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("ldy", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("x_scale", ctypes.c_void_p),
+                ("x_inv_norm", ctypes.c_void_p), ("x_maxabs", ctypes.c_void_p),
+                ("y_scale", ctypes.c_void_p), ("y_maxabs", ctypes.c_void_p),
+                ("y_norm", ctypes.c_void_p), ("y_inv_norm", ctypes.c_void_p)]
+
+
+def _np_ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _tptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream=None) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# decomposition (host)
+# ---------------------------------------------------------------------------
+
+class Decomposition:
+    """Host-side arrow decomposition (LA-Decompose, Section 4.1)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def from_csr(cls, n: int, row_ptr, col, val, b: int, seed: int = 0,
+                 la: int = LA_RANDOM_FOREST, max_levels: int = 0) -> "Decomposition":
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float32)
+        if rp.shape[0] != n + 1:
+            raise ValueError("row_ptr must have n + 1 entries")
+        opts = _DecompOpts(b, la, seed & ((1 << 64) - 1), max_levels, 0)
+        h = ctypes.c_void_p()
+        _check(_load().arrow_decompose(n, _np_ptr(rp), _np_ptr(c) if c.size else None,
+                                       _np_ptr(v) if v.size else None, ctypes.byref(opts),
+                                       ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_matrix(cls, A, b: int, seed: int = 0, la: int = LA_RANDOM_FOREST,
+                    max_levels: int = 0) -> "Decomposition":
+        return cls.from_csr(A.n, A.row_ptr, A.col, A.val, b, seed, la, max_levels)
+
+    @classmethod
+    def load(cls, path: str) -> "Decomposition":
+        h = ctypes.c_void_p()
+        _check(_load().arrow_decomp_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str) -> None:
+        _check(_load().arrow_decomp_save(self._h, os.fsencode(path)))
+
+    def info(self) -> dict:
+        i = _DecompInfo()
+        _check(_load().arrow_decomp_info(self._h, ctypes.byref(i)))
+        return dict(n=i.n, nnz=i.nnz, b=i.b, levels=i.levels, seconds=i.seconds)
+
+    def level(self, i: int) -> dict:
+        """Copy of level i: n_i, vop (vertex of each position), CSR of B_i."""
+        n_i = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        vop, rp, col, val = (ctypes.c_void_p() for _ in range(4))
+        _check(_load().arrow_decomp_level(self._h, i, ctypes.byref(n_i), ctypes.byref(nnz),
+                                          ctypes.byref(vop), ctypes.byref(rp),
+                                          ctypes.byref(col), ctypes.byref(val)))
+
+        def arr(ptr, count, ctype, dtype):
+            if count == 0:
+                return np.zeros(0, dtype=dtype)
+            buf = (ctype * count).from_address(ptr.value)
+            return np.frombuffer(buf, dtype=dtype).copy()
+
+        return dict(n_i=n_i.value,
+                    vop=arr(vop, n_i.value, ctypes.c_int32, np.int32),
+                    row_ptr=arr(rp, n_i.value + 1, ctypes.c_int64, np.int64),
+                    col=arr(col, nnz.value, ctypes.c_int32, np.int32),
+                    val=arr(val, nnz.value, ctypes.c_float, np.float32))
+
+    def levels(self) -> list:
+        return [self.level(i) for i in range(self.info()["levels"])]
+
+    def close(self):
+        if self._h and self._h.value:
+            _load().arrow_decomp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# device plan
+# ---------------------------------------------------------------------------
+
+def _dtype_code(dtype) -> int:
+    if isinstance(dtype, int):
+        return dtype
+    return DTYPES[dtype]
+
+
+def torch_dtype(dtype):
+    import torch
+    return {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16,
+            F8E4M3: torch.float8_e4m3fn}[_dtype_code(dtype)]
+
+
+class Plan:
+    """A decomposition uploaded to one GPU (device-resident, immutable)."""
+
+    def __init__(self, decomp: Decomposition, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required for a plan")
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            _check(_load().arrow_plan_create(decomp._h, device, _stream_handle(stream),
+                                             ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        inf = self.info()
+        self.n = inf["n"]
+
+    def info(self) -> dict:
+        i = _PlanInfo()
+        _check(_load().arrow_plan_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _PlanInfo._fields_}
+
+    def kernel_bytes(self, kernel: int, k: int, dtype="f32") -> int:
+        out = ctypes.c_int64()
+        _check(_load().arrow_plan_kernel_bytes(self._h, kernel, k, _dtype_code(dtype),
+                                               ctypes.byref(out)))
+        return out.value
+
+    def workspace_size(self, k: int, dtype="f32") -> int:
+        out = ctypes.c_size_t()
+        _check(_load().arrow_workspace_size(self._h, k, _dtype_code(dtype), ctypes.byref(out)))
+        return out.value
+
+    def iterate_workspace_size(self, k: int, dtype="f32") -> int:
+        out = ctypes.c_size_t()
+        _check(_load().arrow_iterate_workspace_size(self._h, k, _dtype_code(dtype),
+                                                    ctypes.byref(out)))
+        return out.value
+
+    def workspace(self, nbytes: int):
+        import torch
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def empty(self, k: int, dtype="f32"):
+        """An n x k plan-order buffer of the storage type."""
+        import torch
+        return torch.empty((self.n, k), dtype=torch_dtype(dtype), device=f"cuda:{self.device}")
+
+    def permute_in(self, x, out, dtype="f32", x_scale=None, x_maxabs=None, stream=None):
+        """out = P_{pi_0}^T x converted to `dtype` (x: FP32 original order)."""
+        k = x.shape[1]
+        _check(_load().arrow_permute_in(self._h, _tptr(x), x.stride(0), _tptr(out),
+                                        out.stride(0), _dtype_code(dtype), k, _tptr(x_scale),
+                                        _tptr(x_maxabs), _stream_handle(stream)))
+        return out
+
+    def permute_out(self, y_plan, out, dtype="f32", x_scale=None, col_factor=None, stream=None):
+        """out (FP32, original order) = P_{pi_0} y_plan * scale * factor."""
+        k = y_plan.shape[1]
+        _check(_load().arrow_permute_out(self._h, _tptr(y_plan), y_plan.stride(0),
+                                         _dtype_code(dtype), k, _tptr(x_scale),
+                                         _tptr(col_factor), _tptr(out), out.stride(0),
+                                         _stream_handle(stream)))
+        return out
+
+    def spmm(self, ops: Sequence[Operand], workspace, stream=None):
+        arr = (Operand * len(ops))(*ops)
+        _check(_load().arrow_spmm(self._h, ctypes.cast(arr, ctypes.c_void_p), len(ops),
+                                  _tptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _stream_handle(stream)))
+
+    def iterate(self, x, y, iters: int, dtype="f32", renorm: bool = True, norms=None,
+                x_scale=None, y_scale=None, workspace=None, stream=None):
+        k = x.shape[1]
+        if workspace is None:
+            workspace = self.workspace(self.iterate_workspace_size(k, dtype))
+        _check(_load().arrow_spmm_iterate(self._h, _tptr(x), _tptr(y), k, x.stride(0),
+                                          _dtype_code(dtype), _tptr(x_scale), _tptr(y_scale),
+                                          iters, ITER_RENORM if renorm else 0, _tptr(norms),
+                                          _tptr(workspace),
+                                          workspace.numel() * workspace.element_size(),
+                                          _stream_handle(stream)))
+        return y
+
+    def profile(self, enable: bool):
+        _check(_load().arrow_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_query(self, kernel: int):
+        launches = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(_load().arrow_profile_query(self._h, kernel, ctypes.byref(launches),
+                                           ctypes.byref(ms)))
+        return launches.value, ms.value
+
+    def close(self):
+        if self._h and self._h.value:
+            _load().arrow_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def operand(x, y, dtype="f32", x_scale=None, x_inv_norm=None, x_maxabs=None, y_scale=None,
+            y_maxabs=None, y_norm=None, y_inv_norm=None) -> Operand:
+    return Operand(_tptr(x), _tptr(y), x.shape[1], x.stride(0), y.stride(0),
+                   _dtype_code(dtype), 0, _tptr(x_scale), _tptr(x_inv_norm), _tptr(x_maxabs),
+                   _tptr(y_scale), _tptr(y_maxabs), _tptr(y_norm), _tptr(y_inv_norm))
+
+
+def csr_workspace_size(n: int, k: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_load().arrow_csr_workspace_size(n, k, ctypes.byref(out)))
+    return out.value
+
+
+def csr_spmm(n: int, row_ptr, col, val, x, y, sumsq_ws=None, norms=None, stream=None):
+    """Plain CSR baseline on the device (int32 row_ptr / col, FP32 values)."""
+    _check(_load().arrow_csr_spmm(n, _tptr(row_ptr), _tptr(col), _tptr(val), _tptr(x), _tptr(y),
+                                  x.shape[1], x.stride(0), _tptr(sumsq_ws), _tptr(norms),
+                                  _stream_handle(stream)))
+    return y
+
+
+def copy(src, dst, nbytes: int, stream=None):
+    _check(_load().arrow_copy(_tptr(src), _tptr(dst), nbytes, _stream_handle(stream)))
+
+
+def version() -> str:
+    return _load().arrow_version().decode()

@@ -1,0 +1,590 @@
+// extern "C" boundary of libarrow: argument checks, error reporting, handles.
+#include <hip/hip_runtime_api.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "arrow.h"
+#include "internal.h"
+#include "plan.h"
+
+struct arrow_decomp_s {
+    arrow::Decomp d;
+};
+struct arrow_plan_s {
+    arrow::Plan *p;
+};
+
+namespace arrow {
+namespace {
+thread_local std::string g_last_error;
+}
+void set_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace arrow
+
+using arrow::set_error;
+
+namespace {
+
+bool valid_dtype(arrow_dtype_t t) { return t >= ARROW_F32 && t <= ARROW_F8E4M3; }
+bool scaled(arrow_dtype_t t) { return t == ARROW_F16 || t == ARROW_F8E4M3; }
+
+arrow_status_t check_dense(const void *p, int64_t ld, int64_t k, arrow_dtype_t dt, int64_t rows,
+                           const char *what) {
+    if (rows > 0 && !p) {
+        set_error(std::string(what) + " is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (ld < k) {
+        set_error(std::string(what) + ": ld must be >= k");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const int64_t es = arrow::elem_size(dt);
+    if ((reinterpret_cast<uintptr_t>(p) % 16) != 0 || (ld * es) % 16 != 0) {
+        set_error(std::string(what) + ": base pointer and row stride must be 16-byte aligned");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    return ARROW_OK;
+}
+
+arrow_status_t check_k(int64_t k) {
+    if (k <= 0 || k % 16 != 0 || k > (1 << 20)) {
+        set_error("k must be a positive multiple of 16");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    return ARROW_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+bool overlaps(const void *a, int64_t abytes, const void *b, int64_t bbytes) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *arrow_version(void) { return "1.0.0"; }
+
+const char *arrow_last_error(void) { return arrow::g_last_error.c_str(); }
+
+const char *arrow_status_string(arrow_status_t s) {
+    switch (s) {
+    case ARROW_OK: return "ok";
+    case ARROW_ERR_INVALID_ARG: return "invalid argument";
+    case ARROW_ERR_OUT_OF_MEMORY: return "out of memory";
+    case ARROW_ERR_HIP: return "HIP runtime error";
+    case ARROW_ERR_UNSUPPORTED: return "unsupported";
+    case ARROW_ERR_IO: return "I/O error";
+    case ARROW_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+    }
+}
+
+arrow_status_t arrow_decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                               const float *val, const arrow_decompose_opts_t *opts,
+                               arrow_decomp_t *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!opts) {
+        set_error("opts is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow_decomp_s *h = new (std::nothrow) arrow_decomp_s();
+    if (!h) {
+        set_error("host allocation failed");
+        return ARROW_ERR_OUT_OF_MEMORY;
+    }
+    arrow_status_t st;
+    try {
+        st = arrow::decompose(n, row_ptr, col, val, *opts, h->d);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed during decomposition");
+        st = ARROW_ERR_OUT_OF_MEMORY;
+    }
+    if (st != ARROW_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_decomp_info(arrow_decomp_t d, arrow_decomp_info_t *out) {
+    if (!d || !out) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    out->n = d->d.n;
+    out->nnz = d->d.nnz;
+    out->b = d->d.b;
+    out->levels = (int32_t)d->d.levels.size();
+    out->seconds = d->d.seconds;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_decomp_level(arrow_decomp_t d, int32_t level, int64_t *n_i, int64_t *nnz_i,
+                                  const int32_t **vertex_of_pos, const int64_t **row_ptr,
+                                  const int32_t **col, const float **val) {
+    if (!d || !n_i || !nnz_i || !vertex_of_pos || !row_ptr || !col || !val) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (level < 0 || level >= (int32_t)d->d.levels.size()) {
+        set_error("level out of range");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const arrow::Level &L = d->d.levels[level];
+    *n_i = L.n_i;
+    *nnz_i = (int64_t)L.col.size();
+    *vertex_of_pos = L.vop.data();
+    *row_ptr = L.row_ptr.data();
+    *col = L.col.data();
+    *val = L.val.data();
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_decomp_save(arrow_decomp_t d, const char *path) {
+    if (!d || !path) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    return arrow::save_decomp(d->d, path);
+}
+
+arrow_status_t arrow_decomp_load(const char *path, arrow_decomp_t *out) {
+    if (!out || !path) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    arrow_decomp_s *h = new (std::nothrow) arrow_decomp_s();
+    if (!h) {
+        set_error("host allocation failed");
+        return ARROW_ERR_OUT_OF_MEMORY;
+    }
+    arrow_status_t st;
+    try {
+        st = arrow::load_decomp(path, h->d);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed while loading");
+        st = ARROW_ERR_OUT_OF_MEMORY;
+    }
+    if (st != ARROW_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return ARROW_OK;
+}
+
+void arrow_decomp_destroy(arrow_decomp_t d) { delete d; }
+
+arrow_status_t arrow_plan_create(arrow_decomp_t d, int32_t device, void *stream,
+                                 arrow_plan_t *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!d) {
+        set_error("decomposition is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        set_error("device index out of range (or no HIP device)");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow_plan_s *h = new (std::nothrow) arrow_plan_s();
+    if (!h) {
+        set_error("host allocation failed");
+        return ARROW_ERR_OUT_OF_MEMORY;
+    }
+    DeviceGuard g(device);
+    arrow_status_t st;
+    try {
+        st = arrow::plan_create(d->d, device, static_cast<hipStream_t>(stream), h->p);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed while building the plan");
+        st = ARROW_ERR_OUT_OF_MEMORY;
+    }
+    if (st != ARROW_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return ARROW_OK;
+}
+
+void arrow_plan_destroy(arrow_plan_t p) {
+    if (!p) return;
+    arrow::plan_destroy(p->p);
+    delete p;
+}
+
+arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out) {
+    if (!p || !out) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const arrow::Plan &P = *p->p;
+    out->n = P.n;
+    out->nnz = P.nnz;
+    out->b = P.b;
+    out->levels = P.levels;
+    out->footprint_bytes = P.footprint;
+    out->chunked_rows = P.chunked_rows;
+    out->chunks = P.n_chunks;
+    out->upper_rows = P.n_up;
+    out->contributions = P.l0_ncontrib;
+    out->a_inf_norm = P.a_inf;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_plan_kernel_bytes(arrow_plan_t p, int32_t kernel, int64_t k,
+                                       arrow_dtype_t dtype, int64_t *bytes) {
+    if (!p || !bytes) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (kernel < 0 || kernel >= ARROW_KERNEL_COUNT || !valid_dtype(dtype) || k <= 0) {
+        set_error("bad kernel id, dtype or k");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    *bytes = arrow::kernel_bytes(*p->p, kernel, k, dtype);
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_workspace_size(arrow_plan_t p, int64_t k, arrow_dtype_t dtype,
+                                    size_t *bytes) {
+    if (!p || !bytes) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (arrow_status_t st = check_k(k)) return st;
+    if (!valid_dtype(dtype)) {
+        set_error("bad dtype");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    *bytes = arrow::op_workspace(*p->p, k, dtype);
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_iterate_workspace_size(arrow_plan_t p, int64_t k, arrow_dtype_t dtype,
+                                            size_t *bytes) {
+    size_t base = 0;
+    if (arrow_status_t st = arrow_workspace_size(p, k, dtype, &base)) return st;
+    const size_t zb = ((size_t)p->p->n * k * arrow::elem_size(dtype) + 255) & ~size_t(255);
+    const size_t state = ((size_t)k * (2 * 8 + 2 * 4 + 2 * 4) + 255) & ~size_t(255);
+    *bytes = base + zb + state;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_permute_in(arrow_plan_t p, const float *x, int64_t ldx, void *x_plan,
+                                int64_t ld, arrow_dtype_t dtype, int64_t k, float *x_scale,
+                                float *x_maxabs, void *stream) {
+    if (!p) {
+        set_error("plan is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const arrow::Plan &P = *p->p;
+    if (arrow_status_t st = check_k(k)) return st;
+    if (!valid_dtype(dtype)) {
+        set_error("bad dtype");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (arrow_status_t st = check_dense(x, ldx, k, ARROW_F32, P.n, "x")) return st;
+    if (arrow_status_t st = check_dense(x_plan, ld, k, dtype, P.n, "x_plan")) return st;
+    if (scaled(dtype) && !x_scale) {
+        set_error("x_scale is required for F16 / F8E4M3");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (P.n == 0) return ARROW_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard g(P.device);
+    const int kt = arrow::tile_width(k);
+    const int64_t es = arrow::elem_size(dtype);
+    unsigned *bits = reinterpret_cast<unsigned *>(x_maxabs);
+    hipError_t e = hipSuccess;
+    if (scaled(dtype)) {
+        // per-column max |x| -> power-of-two scale; then max |code| into x_maxabs
+        unsigned *tmp = reinterpret_cast<unsigned *>(x_scale);
+        e = arrow::launch_fill_u32(tmp, 0u, k, s);
+        if (e == hipSuccess) e = arrow::launch_colmax(x, ldx, P.n, (int)k, tmp, s);
+        if (e == hipSuccess) e = arrow::launch_scale_from_max(dtype, tmp, x_scale, (int)k, s);
+    }
+    if (e == hipSuccess && bits) e = arrow::launch_fill_u32(bits, 0u, k, s);
+    for (int64_t c0 = 0; e == hipSuccess && c0 < k; c0 += kt)
+        e = arrow::launch_permute_in(kt, dtype, x + c0, ldx, P.vop0, P.n,
+                                     static_cast<char *>(x_plan) + c0 * es, ld,
+                                     scaled(dtype) ? x_scale + c0 : nullptr,
+                                     bits ? bits + c0 : nullptr, s);
+    if (e != hipSuccess) {
+        set_error(std::string("permute_in launch: ") + hipGetErrorString(e));
+        return ARROW_ERR_HIP;
+    }
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_permute_out(arrow_plan_t p, const void *y_plan, int64_t ld,
+                                 arrow_dtype_t dtype, int64_t k, const float *x_scale,
+                                 const double *col_factor, float *y, int64_t ldy, void *stream) {
+    if (!p) {
+        set_error("plan is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const arrow::Plan &P = *p->p;
+    if (arrow_status_t st = check_k(k)) return st;
+    if (!valid_dtype(dtype)) {
+        set_error("bad dtype");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (arrow_status_t st = check_dense(y_plan, ld, k, dtype, P.n, "y_plan")) return st;
+    if (arrow_status_t st = check_dense(y, ldy, k, ARROW_F32, P.n, "y")) return st;
+    if (P.n == 0) return ARROW_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard g(P.device);
+    const int kt = arrow::tile_width(k);
+    const int64_t es = arrow::elem_size(dtype);
+    for (int64_t c0 = 0; c0 < k; c0 += kt) {
+        hipError_t e = arrow::launch_permute_out(
+            kt, dtype, static_cast<const char *>(y_plan) + c0 * es, ld, P.vop0, P.n,
+            x_scale ? x_scale + c0 : nullptr, col_factor ? col_factor + c0 : nullptr, y + c0, ldy,
+            s);
+        if (e != hipSuccess) {
+            set_error(std::string("permute_out launch: ") + hipGetErrorString(e));
+            return ARROW_ERR_HIP;
+        }
+    }
+    return ARROW_OK;
+}
+
+static arrow_status_t check_op(const arrow::Plan &P, const arrow_operand_t &o) {
+    if (arrow_status_t st = check_k(o.k)) return st;
+    if (!valid_dtype(o.dtype)) {
+        set_error("bad dtype");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (arrow_status_t st = check_dense(o.x, o.ldx, o.k, o.dtype, P.n, "x")) return st;
+    if (arrow_status_t st = check_dense(o.y, o.ldy, o.k, o.dtype, P.n, "y")) return st;
+    const int64_t es = arrow::elem_size(o.dtype);
+    if (P.n > 0 && overlaps(o.x, ((P.n - 1) * o.ldx + o.k) * es, o.y, ((P.n - 1) * o.ldy + o.k) * es)) {
+        set_error("x and y must not overlap");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (scaled(o.dtype) && !o.y_scale) {
+        set_error("y_scale is required for F16 / F8E4M3");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t num_ops,
+                          void *workspace, size_t ws_bytes, void *stream) {
+    if (!p || (num_ops > 0 && !ops) || num_ops < 0) {
+        set_error("NULL plan or operands");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow::Plan &P = *p->p;
+    size_t need = 0;
+    for (int32_t i = 0; i < num_ops; ++i) {
+        if (arrow_status_t st = check_op(P, ops[i])) return st;
+        need += arrow::op_workspace(P, ops[i].k, ops[i].dtype);
+    }
+    if (need > 0 && (!workspace || ws_bytes < need)) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    DeviceGuard g(P.device);
+    char *w = static_cast<char *>(workspace);
+    for (int32_t i = 0; i < num_ops; ++i) {
+        const arrow_operand_t &o = ops[i];
+        arrow::OpState st{o.x, o.y, o.k, o.ldx, o.ldy, o.dtype, o.x_scale, o.x_inv_norm,
+                          o.x_maxabs, o.y_scale, o.y_maxabs, o.y_norm, o.y_inv_norm};
+        if (arrow_status_t r = arrow::spmm_one(P, st, w, static_cast<hipStream_t>(stream)))
+            return r;
+        w += arrow::op_workspace(P, o.k, o.dtype);
+    }
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_spmm_iterate(arrow_plan_t p, const void *x, void *y, int64_t k, int64_t ld,
+                                  arrow_dtype_t dtype, const float *x_scale, float *y_scale,
+                                  int32_t iters, uint32_t flags, double *norms, void *workspace,
+                                  size_t ws_bytes, void *stream) {
+    if (!p) {
+        set_error("plan is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow::Plan &P = *p->p;
+    if (iters < 0) {
+        set_error("iters must be >= 0");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (flags & ~uint32_t(ARROW_ITER_RENORM)) {
+        set_error("unknown flags");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow_operand_t probe{};
+    probe.x = x;
+    probe.y = y;
+    probe.k = k;
+    probe.ldx = probe.ldy = ld;
+    probe.dtype = dtype;
+    probe.y_scale = y_scale;
+    if (arrow_status_t st = check_op(P, probe)) return st;
+    size_t need = 0;
+    arrow_iterate_workspace_size(p, k, dtype, &need);
+    if (!workspace || ws_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (iters == 0 || P.n == 0) return ARROW_OK;
+    DeviceGuard g(P.device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t base = arrow::op_workspace(P, k, dtype);
+    char *w = static_cast<char *>(workspace);
+    void *z = w + base;
+    const size_t zb = ((size_t)P.n * k * arrow::elem_size(dtype) + 255) & ~size_t(255);
+    char *stp = w + base + zb;
+    double *inv[2] = {reinterpret_cast<double *>(stp), reinterpret_cast<double *>(stp) + k};
+    float *scl[2] = {reinterpret_cast<float *>(stp + 16 * k),
+                     reinterpret_cast<float *>(stp + 16 * k) + k};
+    float *mx[2] = {reinterpret_cast<float *>(stp + 24 * k),
+                    reinterpret_cast<float *>(stp + 24 * k) + k};
+    const bool renorm = flags & ARROW_ITER_RENORM;
+    const bool sc = scaled(dtype);
+    for (int32_t t = 0; t < iters; ++t) {
+        arrow::OpState op{};
+        op.x = t == 0 ? x : ((iters - t) % 2 == 0 ? y : z);
+        op.y = (iters - 1 - t) % 2 == 0 ? y : z;
+        op.k = k;
+        op.ldx = op.ldy = ld;
+        op.dtype = dtype;
+        op.x_scale = t == 0 ? x_scale : (sc ? scl[(t - 1) % 2] : nullptr);
+        op.x_inv_norm = (t == 0 || !renorm) ? nullptr : inv[(t - 1) % 2];
+        op.x_maxabs = (t == 0 || !sc) ? nullptr : mx[(t - 1) % 2];
+        op.y_scale = sc ? (t == iters - 1 ? y_scale : scl[t % 2]) : nullptr;
+        op.y_maxabs = sc ? mx[t % 2] : nullptr;
+        op.y_norm = norms ? norms + (int64_t)t * k : nullptr;
+        op.y_inv_norm = inv[t % 2];
+        if (arrow_status_t r = arrow::spmm_one(P, op, w, s)) return r;
+    }
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_csr_workspace_size(int64_t n, int64_t k, size_t *bytes) {
+    if (!bytes || n < 0) {
+        set_error("bad argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (arrow_status_t st = check_k(k)) return st;
+    *bytes = arrow::plain_csr_workspace(n, k);
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                              const float *val, const float *x, float *y, int64_t k, int64_t ld,
+                              double *sumsq_ws, double *norms, void *stream) {
+    if (n < 0 || (n > 0 && !row_ptr)) {
+        set_error("bad CSR");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (arrow_status_t st = check_k(k)) return st;
+    if (arrow_status_t st = check_dense(x, ld, k, ARROW_F32, n, "x")) return st;
+    if (arrow_status_t st = check_dense(y, ld, k, ARROW_F32, n, "y")) return st;
+    if (n > 0 && overlaps(x, ((n - 1) * ld + k) * 4, y, ((n - 1) * ld + k) * 4)) {
+        set_error("x and y must not overlap");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    return arrow::plain_csr(n, row_ptr, col, val, x, y, k, ld, sumsq_ws, norms,
+                            static_cast<hipStream_t>(stream));
+}
+
+arrow_status_t arrow_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+    if (bytes < 0 || bytes % 16 != 0 || (bytes > 0 && (!src || !dst)) ||
+        reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16) {
+        set_error("copy: bytes must be a multiple of 16 and pointers 16-byte aligned");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    hipError_t e = arrow::launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        set_error(std::string("copy launch: ") + hipGetErrorString(e));
+        return ARROW_ERR_HIP;
+    }
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_profile_enable(arrow_plan_t p, int32_t enable) {
+    if (!p) {
+        set_error("plan is NULL");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow::Plan &P = *p->p;
+    DeviceGuard g(P.device);
+    if (enable) {
+        for (const arrow::ProfRec &r : P.prof_recs) {
+            P.ev_pool.push_back(r.start);
+            P.ev_pool.push_back(r.stop);
+        }
+        P.prof_recs.clear();
+    }
+    P.prof = enable != 0;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_profile_query(arrow_plan_t p, int32_t kernel, int64_t *launches,
+                                   double *total_ms) {
+    if (!p || !launches || !total_ms) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow::Plan &P = *p->p;
+    DeviceGuard g(P.device);
+    int64_t cnt = 0;
+    double tot = 0.0;
+    for (const arrow::ProfRec &r : P.prof_recs) {
+        if (r.kernel != kernel) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) {
+            set_error("hipEventSynchronize failed");
+            return ARROW_ERR_HIP;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+            set_error("hipEventElapsedTime failed");
+            return ARROW_ERR_HIP;
+        }
+        ++cnt;
+        tot += ms;
+    }
+    *launches = cnt;
+    *total_ms = tot;
+    return ARROW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Launch interface of the HIP kernels (host and device compile units).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace arrow {
+
+enum : int { kF32 = 0, kF16 = 1, kBF16 = 2, kF8E4M3 = 3 };
+enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
+constexpr int kNumXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+// One row pass over a CSR-like set of rows.
+struct RowPass {
+    int64_t nrows;
+    int32_t rows_per_block;
+    int32_t nblocks;
+    const int32_t *ptr;   // [nrows + 1] direct entry offsets
+    const void *idx;      // uint16 codes (level-0 band/head) or int32 pi_0 columns
+    const float *val;
+    const int32_t *cptr;  // [nrows + 1] listed partial rows (or null when unused)
+    const int32_t *cidx;  // rows of the partial buffer
+    int32_t b;
+    int32_t out_row0;     // first partial-buffer row written by this pass
+};
+
+// One column tile of one operand (all pointers offset to the tile's first column).
+struct Tile {
+    const void *x;
+    int64_t ldx;
+    const float *s;       // partial-row buffer (FP32), read by the upper / level-0 passes
+    float *s_out;         // partial-row buffer written by the chunk / upper passes
+    int64_t lds;
+    void *y;
+    int64_t ldy;
+    const float *x_scale;
+    const double *x_inv_norm;
+    const float *x_maxabs;
+    float *y_scale;
+    double *part_sumsq;   // [KT][part_ld]
+    float *part_max;
+    int64_t part_ld;
+    float a_inf;
+};
+
+struct NormArgs {
+    const double *part_sumsq;
+    const float *part_max;
+    int64_t part_ld;
+    int32_t nparts;
+    double *norm, *inv_norm, *norms_hist;
+    float *maxabs;
+};
+
+int rows_per_round(int kt, int dtype);
+hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
+                           const Tile &t, hipStream_t s);
+hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t count, hipStream_t s);
+hipError_t launch_colmax(const float *x, int64_t ldx, int64_t n, int k, unsigned *out,
+                         hipStream_t s);
+hipError_t launch_scale_from_max(int dtype, unsigned *bits, float *scale, int k, hipStream_t s);
+hipError_t launch_permute_in(int kt, int dtype, const float *x, int64_t ldx, const int32_t *vop,
+                             int64_t n, void *xp, int64_t ld, const float *scale,
+                             unsigned *codemax, hipStream_t s);
+hipError_t launch_permute_out(int kt, int dtype, const void *yp, int64_t ld, const int32_t *vop,
+                              int64_t n, const float *scale, const double *factor, float *y,
+                              int64_t ldy, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+
+}  // namespace arrow

@@ -1,0 +1,680 @@
+// HIP kernels of the arrow-decomposition SpMM for gfx950 (CDNA4, wave64).
+//
+// Y = A X over A = sum_i P_{pi_i} B_i P_{pi_i}^T (Section 3, Eq. (1)) runs as
+// three row passes and a norm pass, all in level-0 (pi_0) order:
+//
+//   chunk pass   the head rows (rows < b, the row tiles B^(0,j) of
+//                Section 3.1) and any long row, split into nnz chunks of
+//                bounded length; each chunk writes one FP32 partial row.
+//   upper pass   the rows of levels i >= 1; their columns were mapped through
+//                pi_0 o pi_i^{-1} at plan time, so X is gathered directly in
+//                level-0 order (the forward permutation of Alg. 2 as a fused
+//                gather); partial rows of chunked rows are added; FP32 output.
+//   level-0 pass the band and head-column entries of B_0 (rows >= b, stored as
+//                16-bit codes relative to the row), plus the listed partial
+//                rows of the other passes (the reverse accumulation of Alg. 2
+//                and the Reduce of Alg. 1), scaled by the per-column factor,
+//                stored once in the storage type, with FP64 per-block column
+//                sums of squares (and max |code| for scaled formats).
+//   norm pass    fixed-order FP64 reduction of the block partials per column.
+//
+// Lane layout: every lane owns 16 bytes of an X row (VEC elements), LPR =
+// KT / VEC lanes cover a row's column tile, a wave handles 64 / LPR rows at a
+// time.  Matrix entries and X rows are read with plain loads (X rows are
+// reused through L2 by neighbouring rows of the band); Y is written with
+// non-temporal stores.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace arrow {
+namespace dev {
+
+constexpr int kWave = 64;
+constexpr int kBlockThreads = 256;
+constexpr int kWaves = kBlockThreads / kWave;
+
+// Native clang vectors (the non-temporal builtins need them).
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef unsigned vu4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store_nt(void *p, vf4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<vf4 *>(p));
+}
+__device__ __forceinline__ void store_nt(void *p, vu4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<vu4 *>(p));
+}
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t code) {
+    return __uint_as_float(code << 16);
+}
+__device__ __forceinline__ uint32_t f32_to_bf16(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float f16_to_f32(uint32_t code) {
+    _Float16 h = __builtin_bit_cast(_Float16, (uint16_t)code);
+    return (float)h;
+}
+__device__ __forceinline__ uint32_t f32_to_f16(float f) {  // round to nearest even
+    _Float16 h = (_Float16)f;
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+// OCP E4M3FN: bias 7, subnormal quantum 2^-9, max 448.
+__device__ __forceinline__ float f8_to_f32(uint32_t code) {
+    uint32_t u = code & 0x7Fu;
+    float normal = __uint_as_float((u << 20) + (120u << 23));
+    float sub = (float)u * 0x1p-9f;
+    float a = u >= 8u ? normal : sub;
+    return (code & 0x80u) ? -a : a;
+}
+__device__ __forceinline__ uint32_t f32_to_f8(float f) {  // RNE, saturating to 448
+    uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
+    float a = fminf(fabsf(f), 448.0f);
+    uint32_t code;
+    if (a >= 0x1p-6f) {
+        uint32_t u = __float_as_uint(a);
+        u += 0x7FFFFu + ((u >> 20) & 1u);
+        u &= ~0xFFFFFu;
+        uint32_t e = (u >> 23) - 120u;  // biased E4M3 exponent
+        code = (e << 3) | ((u >> 20) & 7u);
+        code = code > 0x7Eu ? 0x7Eu : code;
+    } else {
+        code = (uint32_t)__builtin_rintf(a * 512.0f);  // 0 .. 8 (8 = smallest normal)
+    }
+    return code | sign;
+}
+
+template <int DT> struct Fmt;
+template <> struct Fmt<kF32> {
+    static constexpr int kVec = 4;
+    static constexpr float kMax = 3.402823466e38f;
+    static constexpr bool kScaled = false;
+    __device__ static void load(const void *p, float (&v)[kVec]) {
+        float4 a = *reinterpret_cast<const float4 *>(p);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    }
+    // Rounds v in place to the stored value and writes it.
+    __device__ static void store(void *p, float (&v)[kVec]) {
+        vf4 a = {v[0], v[1], v[2], v[3]};
+        store_nt(p, a);
+    }
+};
+template <> struct Fmt<kBF16> {
+    static constexpr int kVec = 8;
+    static constexpr float kMax = 3.38953139e38f;
+    static constexpr bool kScaled = false;
+    __device__ static void load(const void *p, float (&v)[kVec]) {
+        uint4 a = *reinterpret_cast<const uint4 *>(p);
+        uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = bf16_to_f32(w[i] & 0xFFFFu);
+            v[2 * i + 1] = bf16_to_f32(w[i] >> 16);
+        }
+    }
+    __device__ static void store(void *p, float (&v)[kVec]) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t lo = f32_to_bf16(v[2 * i]), hi = f32_to_bf16(v[2 * i + 1]);
+            v[2 * i] = bf16_to_f32(lo);
+            v[2 * i + 1] = bf16_to_f32(hi);
+            w[i] = lo | (hi << 16);
+        }
+        vu4 a = {w[0], w[1], w[2], w[3]};
+        store_nt(p, a);
+    }
+};
+template <> struct Fmt<kF16> {
+    static constexpr int kVec = 8;
+    static constexpr float kMax = 65504.0f;
+    static constexpr bool kScaled = true;
+    __device__ static void load(const void *p, float (&v)[kVec]) {
+        uint4 a = *reinterpret_cast<const uint4 *>(p);
+        uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = f16_to_f32(w[i] & 0xFFFFu);
+            v[2 * i + 1] = f16_to_f32(w[i] >> 16);
+        }
+    }
+    __device__ static void store(void *p, float (&v)[kVec]) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t lo = f32_to_f16(v[2 * i]), hi = f32_to_f16(v[2 * i + 1]);
+            v[2 * i] = f16_to_f32(lo);
+            v[2 * i + 1] = f16_to_f32(hi);
+            w[i] = lo | (hi << 16);
+        }
+        vu4 a = {w[0], w[1], w[2], w[3]};
+        store_nt(p, a);
+    }
+};
+template <> struct Fmt<kF8E4M3> {
+    static constexpr int kVec = 16;
+    static constexpr float kMax = 448.0f;
+    static constexpr bool kScaled = true;
+    __device__ static void load(const void *p, float (&v)[kVec]) {
+        uint4 a = *reinterpret_cast<const uint4 *>(p);
+        uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[4 * i + j] = f8_to_f32((w[i] >> (8 * j)) & 0xFFu);
+    }
+    __device__ static void store(void *p, float (&v)[kVec]) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint32_t c = f32_to_f8(v[4 * i + j]);
+                v[4 * i + j] = f8_to_f32(c);
+                acc |= c << (8 * j);
+            }
+            w[i] = acc;
+        }
+        vu4 a = {w[0], w[1], w[2], w[3]};
+        store_nt(p, a);
+    }
+};
+
+// Smallest power of two >= x (x > 0, finite); 1 for x <= 0.
+__device__ __forceinline__ float pow2_ceil(double x) {
+    if (!(x > 0.0)) return 1.0f;
+    int e;
+    double m = frexp(x, &e);  // x = m 2^e, m in [0.5, 1)
+    if (m == 0.5) e -= 1;
+    return (float)ldexp(1.0, e);
+}
+
+// Workgroup -> row block, keeping each XCD on a contiguous range of blocks:
+// dispatch places workgroup w on XCD w % 8, so XCD x receives the blocks
+// [x*q + min(x, r), ...) in order and its L2 sees neighbouring rows of the band.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+    const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
+    const int x = bid % kNumXcd, j = bid / kNumXcd;
+    return x * q + (x < r ? x : r) + j;
+}
+
+// ---------------------------------------------------------------------------
+// row kernel
+// ---------------------------------------------------------------------------
+
+template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL>
+__global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) {
+    using F = Fmt<DT>;
+    constexpr int VEC = F::kVec;
+    constexpr int LPR = KT / VEC;             // lanes per row
+    constexpr int RPW = kWave / LPR;          // rows per wave and round
+    constexpr int RPR = RPW * kWaves;         // rows per workgroup and round
+    static_assert(LPR >= 1 && kWave % LPR == 0, "tile width");
+    constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
+
+    const int blk = xcd_block(blockIdx.x, rp.nblocks);
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int g = lane / LPR;
+    const int sub = lane % LPR;
+    const int64_t row0 = (int64_t)blk * rp.rows_per_block;
+    const int64_t row1 = row0 + rp.rows_per_block < rp.nrows ? row0 + rp.rows_per_block : rp.nrows;
+
+    const char *xb = reinterpret_cast<const char *>(t.x) + (int64_t)sub * 16;
+    const int64_t xstride = t.ldx * kElem;
+
+    // per-column factors of the final pass (this lane's VEC columns)
+    float fac[VEC], cinv[VEC], cscale[VEC];
+    double ssq[VEC];
+    float cmax[VEC];
+    if constexpr (FINAL) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const int j = sub * VEC + i;
+            const float xs = t.x_scale ? t.x_scale[j] : 1.0f;
+            const double inv = t.x_inv_norm ? t.x_inv_norm[j] : 1.0;
+            fac[i] = (float)((double)xs * inv);
+            if constexpr (F::kScaled) {
+                const float xm = t.x_maxabs ? t.x_maxabs[j] : F::kMax;
+                const float c = pow2_ceil((double)t.a_inf * (double)xs * (double)xm * inv /
+                                          (double)F::kMax);
+                cscale[i] = c;
+                cinv[i] = 1.0f / c;  // exact: c is a power of two
+            } else {
+                cscale[i] = 1.0f;
+                cinv[i] = 1.0f;
+            }
+            ssq[i] = 0.0;
+            cmax[i] = 0.0f;
+        }
+        if constexpr (F::kScaled) {
+            if (blk == 0 && wave == 0 && g == 0 && t.y_scale) {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) t.y_scale[sub * VEC + i] = cscale[i];
+            }
+        }
+    }
+
+    for (int64_t r = row0 + wave * RPW + g; r < row1; r += RPR) {
+        float acc[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+        int e = rp.ptr[r];
+        const int e1 = rp.ptr[r + 1];
+        const int rb = (int)r - rp.b;  // column of code 0 (band start) for 16-bit codes
+        auto column = [&](int ee) -> int64_t {
+            if constexpr (CODE16) {
+                const int code = reinterpret_cast<const uint16_t *>(rp.idx)[ee];
+                return code <= 2 * rp.b ? (int64_t)(rb + code) : (int64_t)(code - 2 * rp.b - 1);
+            } else {
+                return reinterpret_cast<const int32_t *>(rp.idx)[ee];
+            }
+        };
+        for (; e + 4 <= e1; e += 4) {
+            int64_t c[4];
+            float a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = column(e + u);
+                a[u] = rp.val[e + u];
+            }
+            float xv[4][VEC];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) F::load(xb + c[u] * xstride, xv[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[i] = fmaf(a[u], xv[u][i], acc[i]);
+        }
+        for (; e < e1; ++e) {
+            const int64_t c = column(e);
+            const float a = rp.val[e];
+            float xv[VEC];
+            F::load(xb + c * xstride, xv);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = fmaf(a, xv[i], acc[i]);
+        }
+        if constexpr (CONTRIB) {
+            const int c0 = rp.cptr[r], c1 = rp.cptr[r + 1];
+            for (int c = c0; c < c1; ++c) {
+                const float *srow = t.s + (int64_t)rp.cidx[c] * t.lds + sub * VEC;
+#pragma unroll
+                for (int i = 0; i < VEC; i += 4) {
+                    float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
+                    acc[i] += s4.x;
+                    acc[i + 1] += s4.y;
+                    acc[i + 2] += s4.z;
+                    acc[i + 3] += s4.w;
+                }
+            }
+        }
+        if constexpr (FINAL) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * fac[i] * cinv[i];
+            char *yp = reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
+            F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                const double v = (double)acc[i] * (double)cscale[i];
+                ssq[i] += v * v;
+                cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
+            }
+        } else {
+            float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
+#pragma unroll
+            for (int i = 0; i < VEC; i += 4)
+                *reinterpret_cast<float4 *>(sp + i) =
+                    make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
+        }
+    }
+
+    if constexpr (FINAL) {
+        // fixed-order reduction: butterfly across the row groups of a wave,
+        // then the waves in index order
+        __shared__ double s_ssq[kWaves][KT];
+        __shared__ float s_max[kWaves][KT];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            double v = ssq[i];
+            float m = cmax[i];
+#pragma unroll
+            for (int off = LPR; off < kWave; off <<= 1) {
+                v += __shfl_xor(v, off);
+                m = fmaxf(m, __shfl_xor(m, off));
+            }
+            if (g == 0) {
+                s_ssq[wave][sub * VEC + i] = v;
+                s_max[wave][sub * VEC + i] = m;
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < KT; j += kBlockThreads) {
+            double v = s_ssq[0][j];
+            float m = s_max[0][j];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) {
+                v += s_ssq[w][j];
+                m = fmaxf(m, s_max[w][j]);
+            }
+            if (t.part_sumsq) t.part_sumsq[(int64_t)j * t.part_ld + blk] = v;
+            if (t.part_max) t.part_max[(int64_t)j * t.part_ld + blk] = m;
+        }
+    }
+}
+
+// One workgroup per column: fixed-order FP64 sum of the block partials.
+__global__ __launch_bounds__(kBlockThreads) void norm_kernel(NormArgs a) {
+    const int j = blockIdx.x;
+    const double *ps = a.part_sumsq + (int64_t)j * a.part_ld;
+    double v = 0.0;
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < a.nparts; i += kBlockThreads) v += ps[i];
+    if (a.part_max) {
+        const float *pm = a.part_max + (int64_t)j * a.part_ld;
+        for (int i = threadIdx.x; i < a.nparts; i += kBlockThreads) m = fmaxf(m, pm[i]);
+    }
+    __shared__ double sv[kBlockThreads];
+    __shared__ float sm[kBlockThreads];
+    sv[threadIdx.x] = v;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kBlockThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sv[threadIdx.x] += sv[threadIdx.x + s];
+            sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double ss = sv[0];
+        const double nu = sqrt(ss);
+        if (a.norm) a.norm[j] = nu;
+        if (a.inv_norm) a.inv_norm[j] = nu > 0.0 ? 1.0 / nu : 0.0;
+        if (a.norms_hist) a.norms_hist[j] = nu;
+        if (a.maxabs) a.maxabs[j] = sm[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// permutation kernels (Section 5.1: work in pi_0 order, permute at the ends)
+// ---------------------------------------------------------------------------
+
+// Per-column max |x| of an FP32 matrix: float bits of non-negative values
+// order like unsigned integers, so an atomic max is order independent.
+__global__ __launch_bounds__(kBlockThreads) void colmax_kernel(const float *x, int64_t ldx,
+                                                                int64_t n, int k,
+                                                                unsigned *out) {
+    const int j = threadIdx.x % 64;
+    const int rsub = threadIdx.x / 64;
+    for (int jj = j; jj < k; jj += 64) {
+        float m = 0.0f;
+        for (int64_t r = (int64_t)blockIdx.x * 4 + rsub; r < n; r += (int64_t)gridDim.x * 4)
+            m = fmaxf(m, fabsf(x[r * ldx + jj]));
+        atomicMax(out + jj, __float_as_uint(m));
+    }
+}
+
+__global__ void fill_u32_kernel(unsigned *p, unsigned v, int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// colmax (float bits of max |x|) -> power-of-two scale s_j with max/s_j <= kMax.
+// `bits` and `scale` may be the same buffer.
+template <int DT>
+__global__ void scale_from_max_kernel(const unsigned *bits, float *scale, int k) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < k) {
+        const float m = __uint_as_float(bits[j]);
+        scale[j] = pow2_ceil((double)m / (double)Fmt<DT>::kMax);
+    }
+}
+
+// x_plan[p] = convert(x[vop[p]] / scale): one lane group per row.
+template <int KT, int DT>
+__global__ __launch_bounds__(kBlockThreads) void permute_in_kernel(
+    const float *x, int64_t ldx, const int32_t *vop, int64_t n, void *xp, int64_t ld,
+    const float *scale, unsigned *codemax) {
+    using F = Fmt<DT>;
+    constexpr int VEC = F::kVec;
+    constexpr int LPR = KT / VEC;
+    constexpr int RPB = kBlockThreads / LPR;
+    constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
+    const int sub = threadIdx.x % LPR;
+    const int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+    float m[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) m[i] = 0.0f;
+    if (p < n) {
+        const float *src = x + (int64_t)vop[p] * ldx + sub * VEC;
+        float v[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; i += 4) {
+            float4 a = *reinterpret_cast<const float4 *>(src + i);
+            v[i] = a.x; v[i + 1] = a.y; v[i + 2] = a.z; v[i + 3] = a.w;
+        }
+        if (scale) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) v[i] = v[i] / scale[sub * VEC + i];
+        }
+        F::store(reinterpret_cast<char *>(xp) + (p * ld * kElem) + sub * 16, v);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) m[i] = fabsf(v[i]);
+    }
+    if (codemax) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            float mm = m[i];
+#pragma unroll
+            for (int off = LPR; off < kWave; off <<= 1) mm = fmaxf(mm, __shfl_xor(mm, off));
+            if ((threadIdx.x % kWave) < LPR) atomicMax(codemax + sub * VEC + i, __float_as_uint(mm));
+        }
+    }
+}
+
+// y[vop[p]] = yp[p] * scale * factor (FP32 out).
+template <int KT, int DT>
+__global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
+    const void *yp, int64_t ld, const int32_t *vop, int64_t n, const float *scale,
+    const double *factor, float *y, int64_t ldy) {
+    using F = Fmt<DT>;
+    constexpr int VEC = F::kVec;
+    constexpr int LPR = KT / VEC;
+    constexpr int RPB = kBlockThreads / LPR;
+    constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
+    const int sub = threadIdx.x % LPR;
+    const int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+    if (p >= n) return;
+    float v[VEC];
+    F::load(reinterpret_cast<const char *>(yp) + p * ld * kElem + sub * 16, v);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const int j = sub * VEC + i;
+        double f = 1.0;
+        if (scale) f *= (double)scale[j];
+        if (factor) f *= factor[j];
+        v[i] = (float)((double)v[i] * f);
+    }
+    float *dst = y + (int64_t)vop[p] * ldy + sub * VEC;
+#pragma unroll
+    for (int i = 0; i < VEC; i += 4)
+        *reinterpret_cast<float4 *>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+}
+
+// Streaming copy (HBM calibration): 16 bytes per lane and iteration.
+__global__ __launch_bounds__(kBlockThreads) void copy_kernel(const vu4 *src, vu4 *dst,
+                                                             int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * kBlockThreads)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+}  // namespace dev
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+namespace {
+
+template <int KT, int DT>
+hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const Tile &t,
+                        hipStream_t s) {
+    dim3 grid(rp.nblocks), block(dev::kBlockThreads);
+    if (rp.nblocks <= 0) return hipSuccess;
+    switch (mode) {
+    case kPassChunk:
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, false>), grid, block, 0, s, rp, t);
+        break;
+    case kPassUpper:
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false>), grid, block, 0, s, rp, t);
+        break;
+    case kPassLevel0:
+        if (code16)
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true>), grid, block, 0, s, rp, t);
+        else
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, true>), grid, block, 0, s, rp, t);
+        break;
+    case kPassPlain:  // plain CSR: int32 columns, no contributions, final store
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, true>), grid, block, 0, s, rp, t);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_row_dt(int kt, int mode, bool code16, const RowPass &rp, const Tile &t,
+                         hipStream_t s) {
+    switch (kt) {
+    case 16: return launch_row_t<16, DT>(mode, code16, rp, t, s);
+    case 32: return launch_row_t<32, DT>(mode, code16, rp, t, s);
+    case 64: return launch_row_t<64, DT>(mode, code16, rp, t, s);
+    case 128: return launch_row_t<128, DT>(mode, code16, rp, t, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int KT, int DT>
+hipError_t launch_perm_in_t(const float *x, int64_t ldx, const int32_t *vop, int64_t n, void *xp,
+                            int64_t ld, const float *scale, unsigned *codemax, hipStream_t s) {
+    constexpr int LPR = KT / dev::Fmt<DT>::kVec;
+    constexpr int RPB = dev::kBlockThreads / LPR;
+    dim3 grid((unsigned)((n + RPB - 1) / RPB));
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((dev::permute_in_kernel<KT, DT>), grid, dim3(dev::kBlockThreads), 0, s, x,
+                       ldx, vop, n, xp, ld, scale, codemax);
+    return hipGetLastError();
+}
+
+template <int KT, int DT>
+hipError_t launch_perm_out_t(const void *yp, int64_t ld, const int32_t *vop, int64_t n,
+                             const float *scale, const double *factor, float *y, int64_t ldy,
+                             hipStream_t s) {
+    constexpr int LPR = KT / dev::Fmt<DT>::kVec;
+    constexpr int RPB = dev::kBlockThreads / LPR;
+    dim3 grid((unsigned)((n + RPB - 1) / RPB));
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((dev::permute_out_kernel<KT, DT>), grid, dim3(dev::kBlockThreads), 0, s,
+                       yp, ld, vop, n, scale, factor, y, ldy);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int rows_per_round(int kt, int dtype) {
+    const int vec = dtype == kF32 ? 4 : (dtype == kF8E4M3 ? 16 : 8);
+    const int lpr = kt / vec;
+    return (dev::kWave / lpr) * dev::kWaves;
+}
+
+hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
+                           const Tile &t, hipStream_t s) {
+    switch (dtype) {
+    case kF32: return launch_row_dt<kF32>(kt, mode, code16, rp, t, s);
+    case kF16: return launch_row_dt<kF16>(kt, mode, code16, rp, t, s);
+    case kBF16: return launch_row_dt<kBF16>(kt, mode, code16, rp, t, s);
+    case kF8E4M3: return launch_row_dt<kF8E4M3>(kt, mode, code16, rp, t, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::norm_kernel, dim3(k), dim3(dev::kBlockThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::fill_u32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       s, p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_colmax(const float *x, int64_t ldx, int64_t n, int k, unsigned *out,
+                         hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    int64_t blocks = (n + 4 * 64 - 1) / (4 * 64);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(dev::colmax_kernel, dim3((unsigned)blocks), dim3(dev::kBlockThreads), 0, s,
+                       x, ldx, n, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_from_max(int dtype, unsigned *bits, float *scale, int k, hipStream_t s) {
+    dim3 grid((k + 255) / 256), block(256);
+    if (dtype == kF16)
+        hipLaunchKernelGGL(dev::scale_from_max_kernel<kF16>, grid, block, 0, s, bits, scale, k);
+    else if (dtype == kF8E4M3)
+        hipLaunchKernelGGL(dev::scale_from_max_kernel<kF8E4M3>, grid, block, 0, s, bits, scale, k);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_in(int kt, int dtype, const float *x, int64_t ldx, const int32_t *vop,
+                             int64_t n, void *xp, int64_t ld, const float *scale,
+                             unsigned *codemax, hipStream_t s) {
+#define ARROW_PIN(KT_, DT_) \
+    if (kt == KT_ && dtype == DT_) return launch_perm_in_t<KT_, DT_>(x, ldx, vop, n, xp, ld, scale, codemax, s);
+#define ARROW_PIN_DT(DT_) ARROW_PIN(16, DT_) ARROW_PIN(32, DT_) ARROW_PIN(64, DT_) ARROW_PIN(128, DT_)
+    ARROW_PIN_DT(kF32) ARROW_PIN_DT(kF16) ARROW_PIN_DT(kBF16) ARROW_PIN_DT(kF8E4M3)
+#undef ARROW_PIN_DT
+#undef ARROW_PIN
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_permute_out(int kt, int dtype, const void *yp, int64_t ld, const int32_t *vop,
+                              int64_t n, const float *scale, const double *factor, float *y,
+                              int64_t ldy, hipStream_t s) {
+#define ARROW_POUT(KT_, DT_) \
+    if (kt == KT_ && dtype == DT_) return launch_perm_out_t<KT_, DT_>(yp, ld, vop, n, scale, factor, y, ldy, s);
+#define ARROW_POUT_DT(DT_) ARROW_POUT(16, DT_) ARROW_POUT(32, DT_) ARROW_POUT(64, DT_) ARROW_POUT(128, DT_)
+    ARROW_POUT_DT(kF32) ARROW_POUT_DT(kF16) ARROW_POUT_DT(kBF16) ARROW_POUT_DT(kF8E4M3)
+#undef ARROW_POUT_DT
+#undef ARROW_POUT
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s) {
+    const int64_t count = bytes / 16;
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + dev::kBlockThreads - 1) / dev::kBlockThreads;
+    if (blocks > 256 * 32) blocks = 256 * 32;
+    hipLaunchKernelGGL(dev::copy_kernel, dim3((unsigned)blocks), dim3(dev::kBlockThreads), 0, s,
+                       reinterpret_cast<const dev::vu4 *>(src), reinterpret_cast<dev::vu4 *>(dst), count);
+    return hipGetLastError();
+}
+
+}  // namespace arrow

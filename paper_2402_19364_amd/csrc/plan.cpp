@@ -1,0 +1,477 @@
+// Plan construction (host) and launch orchestration.
+//
+// The decomposition's levels become three row passes in level-0 order:
+//  * chunk pass: the head rows of B_0 (rows < b: the row tiles of Section 3.1,
+//    whose entries may reach any column) and every row longer than kLongRow,
+//    cut into chunks of kChunk entries (the hub rows behind the load imbalance
+//    discussed in Section 6.2);
+//  * upper pass: each row of B_i (i >= 1) that holds entries, with columns
+//    mapped to level-0 positions through sigma_i = pi_0 o pi_i^{-1};
+//  * level-0 pass: the band and head-column entries of B_0 (rows >= b) as
+//    16-bit codes relative to the row, plus a list per row of the partial rows
+//    to add: its own chunks, then the upper-pass rows of the same vertex by
+//    level (the accumulation of Alg. 2, in a fixed order).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+namespace arrow {
+namespace {
+
+#define HIP_OK(expr)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));          \
+            return ARROW_ERR_HIP;                                                  \
+        }                                                                          \
+    } while (0)
+
+template <class T>
+arrow_status_t upload(Plan &p, T *&dst, const std::vector<T> &src, hipStream_t s) {
+    dst = nullptr;
+    if (src.empty()) return ARROW_OK;
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, src.size() * sizeof(T));
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc of plan array: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? ARROW_ERR_OUT_OF_MEMORY : ARROW_ERR_HIP;
+    }
+    p.allocs.push_back(d);
+    p.footprint += (int64_t)(src.size() * sizeof(T));
+    HIP_OK(hipMemcpyAsync(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    dst = static_cast<T *>(d);
+    return ARROW_OK;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t count_true(const std::vector<uint8_t> &m) {
+    int64_t c = 0;
+    for (uint8_t v : m) c += v;
+    return c;
+}
+
+}  // namespace
+
+int64_t elem_size(int dtype) { return dtype == kF32 ? 4 : (dtype == kF8E4M3 ? 1 : 2); }
+
+int tile_width(int64_t k) {
+    for (int kt : {128, 64, 32, 16})
+        if (k % kt == 0) return kt;
+    return 0;
+}
+
+static int64_t nblocks_of(int64_t rows, int64_t rpb) { return (rows + rpb - 1) / rpb; }
+
+arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out) {
+    out = nullptr;
+    Plan *pp = new (std::nothrow) Plan();
+    if (!pp) {
+        set_error("host allocation of the plan failed");
+        return ARROW_ERR_OUT_OF_MEMORY;
+    }
+    Plan &p = *pp;
+    p.device = device;
+    p.n = d.n;
+    p.nnz = d.nnz;
+    p.b = d.b;
+    p.levels = (int32_t)d.levels.size();
+    p.code16 = 3LL * d.b <= 65535;
+    const int64_t n = d.n, b = d.b;
+    const Level &L0 = d.levels[0];
+
+    std::vector<int32_t> pos0(n);
+    for (int64_t q = 0; q < n; ++q) pos0[L0.vop[q]] = (int32_t)q;
+
+    // |A| row sums for the FP8/FP16 scale bound
+    {
+        std::vector<double> rs(n, 0.0);
+        for (const Level &L : d.levels)
+            for (int64_t q = 0; q < L.n_i; ++q)
+                for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e)
+                    rs[L.vop[q]] += std::fabs((double)L.val[e]);
+        for (double v : rs) p.a_inf = std::max(p.a_inf, v);
+    }
+
+    // upper rows (levels >= 1 with entries), in (level, position) order
+    struct UpRow { int32_t level; int32_t pos; };
+    std::vector<UpRow> up;
+    for (int32_t i = 1; i < p.levels; ++i) {
+        const Level &L = d.levels[i];
+        for (int64_t q = 0; q < L.n_i; ++q)
+            if (L.row_ptr[q + 1] > L.row_ptr[q]) up.push_back({i, (int32_t)q});
+    }
+    p.n_up = (int64_t)up.size();
+
+    // chunks: level-0 chunked rows, then chunked upper rows
+    std::vector<int32_t> ch_ptr(1, 0), ch_col;
+    std::vector<float> ch_val;
+    std::vector<int32_t> l0_chunk_first(n, -1), l0_chunk_count(n, 0);
+    auto add_chunks = [&](const Level &L, int64_t q, bool map) -> std::pair<int32_t, int32_t> {
+        const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
+        const int32_t first = (int32_t)(ch_ptr.size() - 1);
+        for (int64_t e = e0; e < e1; e += kChunk) {
+            const int64_t ee = std::min<int64_t>(e + kChunk, e1);
+            for (int64_t j = e; j < ee; ++j) {
+                const int32_t c = L.col[j];
+                ch_col.push_back(map ? pos0[L.vop[c]] : c);
+                ch_val.push_back(L.val[j]);
+            }
+            ch_ptr.push_back((int32_t)ch_col.size());
+        }
+        return {first, (int32_t)(ch_ptr.size() - 1) - first};
+    };
+    std::vector<int32_t> l0_ptr(n + 1, 0);
+    std::vector<uint16_t> l0_code;
+    std::vector<int32_t> l0_col;
+    std::vector<float> l0_val;
+    std::vector<uint8_t> seen_l0(n, 0), seen_up(n, 0), seen_ch(n, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t e0 = L0.row_ptr[r], e1 = L0.row_ptr[r + 1];
+        const bool chunked = (r < b && e1 > e0) || (e1 - e0 > kLongRow);
+        if (chunked) {
+            auto fc = add_chunks(L0, r, false);
+            l0_chunk_first[r] = fc.first;
+            l0_chunk_count[r] = fc.second;
+            ++p.chunked_rows;
+        } else {
+            for (int64_t e = e0; e < e1; ++e) {
+                const int64_t q = L0.col[e];
+                if (p.code16) {
+                    const int64_t code = q >= r - b ? q - r + b : 2 * b + 1 + q;
+                    l0_code.push_back((uint16_t)code);
+                } else {
+                    l0_col.push_back((int32_t)q);
+                }
+                l0_val.push_back(L0.val[e]);
+                seen_l0[q] = 1;
+            }
+        }
+        l0_ptr[r + 1] = (int32_t)l0_val.size();
+    }
+    std::vector<int32_t> up_ptr(p.n_up + 1, 0), up_col, up_cptr(p.n_up + 1, 0), up_cidx;
+    std::vector<float> up_val;
+    std::vector<std::pair<int32_t, int32_t>> up_chunks(p.n_up, {-1, 0});
+    for (int64_t s = 0; s < p.n_up; ++s) {
+        const Level &L = d.levels[up[s].level];
+        const int64_t q = up[s].pos;
+        const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
+        if (e1 - e0 > kLongRow) {
+            up_chunks[s] = add_chunks(L, q, true);
+            ++p.chunked_rows;
+        } else {
+            for (int64_t e = e0; e < e1; ++e) {
+                const int32_t c = pos0[L.vop[L.col[e]]];
+                up_col.push_back(c);
+                up_val.push_back(L.val[e]);
+                seen_up[c] = 1;
+            }
+        }
+        up_ptr[s + 1] = (int32_t)up_val.size();
+    }
+    p.n_chunks = (int64_t)ch_ptr.size() - 1;
+    p.s_rows = p.n_up + p.n_chunks;
+    for (int32_t c : ch_col) seen_ch[c] = 1;
+    // partial rows listed by the upper rows: their own chunks
+    for (int64_t s = 0; s < p.n_up; ++s) {
+        for (int32_t c = 0; c < up_chunks[s].second; ++c)
+            up_cidx.push_back((int32_t)(p.n_up + up_chunks[s].first + c));
+        up_cptr[s + 1] = (int32_t)up_cidx.size();
+    }
+    // partial rows listed by the level-0 rows: own chunks, then upper rows by level
+    std::vector<int32_t> l0_cptr(n + 1, 0), l0_cidx;
+    {
+        std::vector<int32_t> cnt(n, 0);
+        for (int64_t r = 0; r < n; ++r) cnt[r] = l0_chunk_count[r];
+        for (int64_t s = 0; s < p.n_up; ++s)
+            ++cnt[pos0[d.levels[up[s].level].vop[up[s].pos]]];
+        for (int64_t r = 0; r < n; ++r) l0_cptr[r + 1] = l0_cptr[r] + cnt[r];
+        l0_cidx.assign(l0_cptr[n], 0);
+        std::vector<int32_t> fill(l0_cptr.begin(), l0_cptr.end() - 1);
+        for (int64_t r = 0; r < n; ++r)
+            for (int32_t c = 0; c < l0_chunk_count[r]; ++c)
+                l0_cidx[fill[r]++] = (int32_t)(p.n_up + l0_chunk_first[r] + c);
+        for (int64_t s = 0; s < p.n_up; ++s) {
+            const int32_t r = pos0[d.levels[up[s].level].vop[up[s].pos]];
+            l0_cidx[fill[r]++] = (int32_t)s;
+        }
+    }
+    p.l0_nnz = (int64_t)l0_val.size();
+    p.l0_ncontrib = (int64_t)l0_cidx.size();
+    p.up_nnz = (int64_t)up_val.size();
+    p.up_ncontrib = (int64_t)up_cidx.size();
+    p.ch_nnz = (int64_t)ch_val.size();
+    p.distinct_l0 = count_true(seen_l0);
+    p.distinct_up = count_true(seen_up);
+    p.distinct_ch = count_true(seen_ch);
+
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        set_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+        delete pp;
+        return ARROW_ERR_HIP;
+    }
+    arrow_status_t st = ARROW_OK;
+#define UP(dst, src)                                \
+    if (st == ARROW_OK) st = upload(p, dst, src, stream);
+    UP(p.l0_ptr, l0_ptr);
+    if (p.code16) {
+        uint16_t *codes = nullptr;
+        UP(codes, l0_code);
+        p.l0_idx = codes;
+    } else {
+        int32_t *cols = nullptr;
+        UP(cols, l0_col);
+        p.l0_idx = cols;
+    }
+    UP(p.l0_val, l0_val);
+    UP(p.l0_cptr, l0_cptr);
+    UP(p.l0_cidx, l0_cidx);
+    UP(p.up_ptr, up_ptr);
+    UP(p.up_col, up_col);
+    UP(p.up_val, up_val);
+    UP(p.up_cptr, up_cptr);
+    UP(p.up_cidx, up_cidx);
+    UP(p.ch_ptr, ch_ptr);
+    UP(p.ch_col, ch_col);
+    UP(p.ch_val, ch_val);
+    UP(p.vop0, L0.vop);
+#undef UP
+    if (st == ARROW_OK) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            set_error(std::string("plan upload: ") + hipGetErrorString(e));
+            st = ARROW_ERR_HIP;
+        }
+    }
+    if (st != ARROW_OK) {
+        plan_destroy(pp);
+        return st;
+    }
+    out = pp;
+    return ARROW_OK;
+}
+
+void plan_destroy(Plan *p) {
+    if (!p) return;
+    hipSetDevice(p->device);
+    for (void *a : p->allocs) hipFree(a);
+    for (const ProfRec &r : p->prof_recs) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t ev : p->ev_pool) hipEventDestroy(ev);
+    delete p;
+}
+
+size_t op_workspace(const Plan &p, int64_t k, int dtype) {
+    (void)dtype;
+    const int64_t nb = nblocks_of(p.n, kRowsPerBlock);
+    return align256((size_t)p.s_rows * k * 4) + align256((size_t)k * nb * 8) +
+           align256((size_t)k * nb * 4);
+}
+
+namespace {
+
+hipEvent_t pool_event(Plan &p) {
+    if (!p.ev_pool.empty()) {
+        hipEvent_t ev = p.ev_pool.back();
+        p.ev_pool.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    return ev;
+}
+
+struct ProfScope {
+    Plan &p;
+    int kernel;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(Plan &pl, int k, hipStream_t st) : p(pl), kernel(k), s(st) {
+        if (!p.prof || p.prof_recs.size() >= 200000) return;
+        a = pool_event(p);
+        b = pool_event(p);
+        if (a && b) hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (a && b) {
+            hipEventRecord(b, s);
+            p.prof_recs.push_back({kernel, a, b, s});
+        }
+    }
+};
+
+#define LAUNCH_OK(expr)                                                            \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            set_error(std::string("kernel launch: ") + hipGetErrorString(e_));     \
+            return ARROW_ERR_HIP;                                                  \
+        }                                                                          \
+    } while (0)
+
+}  // namespace
+
+arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
+    const int64_t n = p.n, k = op.k;
+    if (n == 0) return ARROW_OK;
+    const int kt = tile_width(k);
+    const int64_t es = elem_size(op.dtype);
+    const int64_t nb = nblocks_of(n, kRowsPerBlock);
+    char *w = static_cast<char *>(ws);
+    float *sbuf = reinterpret_cast<float *>(w);
+    w += align256((size_t)p.s_rows * k * 4);
+    double *psum = reinterpret_cast<double *>(w);
+    w += align256((size_t)k * nb * 8);
+    float *pmax = reinterpret_cast<float *>(w);
+
+    RowPass ch{};
+    ch.nrows = p.n_chunks;
+    ch.rows_per_block = rows_per_round(kt, op.dtype);
+    ch.nblocks = (int32_t)nblocks_of(p.n_chunks, ch.rows_per_block);
+    ch.ptr = p.ch_ptr;
+    ch.idx = p.ch_col;
+    ch.val = p.ch_val;
+    ch.b = p.b;
+    ch.out_row0 = (int32_t)p.n_up;
+
+    RowPass upp{};
+    upp.nrows = p.n_up;
+    upp.rows_per_block = kRowsPerBlock;
+    upp.nblocks = (int32_t)nblocks_of(p.n_up, kRowsPerBlock);
+    upp.ptr = p.up_ptr;
+    upp.idx = p.up_col;
+    upp.val = p.up_val;
+    upp.cptr = p.up_cptr;
+    upp.cidx = p.up_cidx;
+    upp.b = p.b;
+    upp.out_row0 = 0;
+
+    RowPass l0{};
+    l0.nrows = n;
+    l0.rows_per_block = kRowsPerBlock;
+    l0.nblocks = (int32_t)nb;
+    l0.ptr = p.l0_ptr;
+    l0.idx = p.l0_idx;
+    l0.val = p.l0_val;
+    l0.cptr = p.l0_cptr;
+    l0.cidx = p.l0_cidx;
+    l0.b = p.b;
+
+    for (int64_t c0 = 0; c0 < k; c0 += kt) {
+        Tile t{};
+        t.x = static_cast<const char *>(op.x) + c0 * es;
+        t.ldx = op.ldx;
+        t.s = sbuf + c0;
+        t.s_out = sbuf + c0;
+        t.lds = k;
+        t.y = static_cast<char *>(op.y) + c0 * es;
+        t.ldy = op.ldy;
+        t.x_scale = op.x_scale ? op.x_scale + c0 : nullptr;
+        t.x_inv_norm = op.x_inv_norm ? op.x_inv_norm + c0 : nullptr;
+        t.x_maxabs = op.x_maxabs ? op.x_maxabs + c0 : nullptr;
+        t.y_scale = op.y_scale ? op.y_scale + c0 : nullptr;
+        t.part_sumsq = psum + c0 * nb;
+        t.part_max = pmax + c0 * nb;
+        t.part_ld = nb;
+        t.a_inf = (float)p.a_inf;
+        if (p.n_chunks > 0) {
+            ProfScope ps(p, ARROW_KERNEL_CHUNKS, s);
+            LAUNCH_OK(launch_row_pass(kt, op.dtype, kPassChunk, false, ch, t, s));
+        }
+        if (p.n_up > 0) {
+            ProfScope ps(p, ARROW_KERNEL_UPPER, s);
+            LAUNCH_OK(launch_row_pass(kt, op.dtype, kPassUpper, false, upp, t, s));
+        }
+        {
+            ProfScope ps(p, ARROW_KERNEL_LEVEL0, s);
+            LAUNCH_OK(launch_row_pass(kt, op.dtype, kPassLevel0, p.code16, l0, t, s));
+        }
+    }
+    NormArgs na{};
+    na.part_sumsq = psum;
+    na.part_max = (op.y_maxabs != nullptr) ? pmax : nullptr;
+    na.part_ld = nb;
+    na.nparts = (int32_t)nb;
+    na.norm = op.y_norm;
+    na.inv_norm = op.y_inv_norm;
+    na.maxabs = op.y_maxabs;
+    if (op.y_norm || op.y_inv_norm || op.y_maxabs) {
+        ProfScope ps(p, ARROW_KERNEL_NORM, s);
+        LAUNCH_OK(launch_norm(na, (int)k, s));
+    }
+    return ARROW_OK;
+}
+
+int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
+    const int64_t sx = elem_size(dtype);
+    const int64_t nb = nblocks_of(p.n, kRowsPerBlock);
+    const bool scaled = dtype == kF16 || dtype == kF8E4M3;
+    switch (kernel) {
+    case ARROW_KERNEL_CHUNKS:
+        if (p.n_chunks == 0) return 0;
+        return p.ch_nnz * 8 + (p.n_chunks + 1) * 4 + p.distinct_ch * k * sx + p.n_chunks * k * 4;
+    case ARROW_KERNEL_UPPER:
+        if (p.n_up == 0) return 0;
+        return p.up_nnz * 8 + (p.n_up + 1) * 8 + p.up_ncontrib * (4 + k * 4) +
+               p.distinct_up * k * sx + p.n_up * k * 4;
+    case ARROW_KERNEL_LEVEL0:
+        return p.l0_nnz * ((p.code16 ? 2 : 4) + 4) + (p.n + 1) * 8 +
+               p.l0_ncontrib * (4 + k * 4) + p.distinct_l0 * k * sx + p.n * k * sx +
+               nb * k * (8 + (scaled ? 4 : 0)) + k * (scaled ? 16 : 8);
+    case ARROW_KERNEL_NORM:
+        return nb * k * (8 + (scaled ? 4 : 0)) + k * 16;
+    case ARROW_KERNEL_PERMUTE:
+        return p.n * 4 + p.n * k * (4 + sx);
+    default:
+        return -1;
+    }
+}
+
+size_t plain_csr_workspace(int64_t n, int64_t k) {
+    const int64_t nb = nblocks_of(n, kRowsPerBlock);
+    return align256((size_t)k * nb * 8);
+}
+
+arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                         const float *x, float *y, int64_t k, int64_t ld, double *ws,
+                         double *norms, hipStream_t s) {
+    if (n == 0) return ARROW_OK;
+    const int kt = tile_width(k);
+    const int64_t nb = nblocks_of(n, kRowsPerBlock);
+    RowPass rp{};
+    rp.nrows = n;
+    rp.rows_per_block = kRowsPerBlock;
+    rp.nblocks = (int32_t)nb;
+    rp.ptr = row_ptr;
+    rp.idx = col;
+    rp.val = val;
+    rp.b = 0;
+    for (int64_t c0 = 0; c0 < k; c0 += kt) {
+        Tile t{};
+        t.x = x + c0;
+        t.ldx = ld;
+        t.y = y + c0;
+        t.ldy = ld;
+        t.part_sumsq = ws ? ws + c0 * nb : nullptr;
+        t.part_ld = nb;
+        LAUNCH_OK(launch_row_pass(kt, kF32, kPassPlain, false, rp, t, s));
+    }
+    if (ws && norms) {
+        NormArgs na{};
+        na.part_sumsq = ws;
+        na.part_ld = nb;
+        na.nparts = (int32_t)nb;
+        na.norm = norms;
+        LAUNCH_OK(launch_norm(na, (int)k, s));
+    }
+    return ARROW_OK;
+}
+
+}  // namespace arrow

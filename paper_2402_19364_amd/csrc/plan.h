@@ -1,0 +1,93 @@
+// Device plan: the decomposition laid out as row passes in level-0 order.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace arrow {
+
+constexpr int kLongRow = 256;     // rows with more entries go through the chunk pass
+constexpr int kChunk = 256;       // entries per chunk
+constexpr int kRowsPerBlock = 512;
+
+struct ProfRec {
+    int kernel;
+    hipEvent_t start, stop;
+    hipStream_t stream;
+};
+
+struct Plan {
+    int device = 0;
+    int64_t n = 0, nnz = 0;
+    int32_t b = 0, levels = 0;
+    double a_inf = 0.0;
+    bool code16 = true;
+
+    // level-0 pass (n rows)
+    int32_t *l0_ptr = nullptr;
+    void *l0_idx = nullptr;
+    float *l0_val = nullptr;
+    int32_t *l0_cptr = nullptr;
+    int32_t *l0_cidx = nullptr;
+    int64_t l0_nnz = 0, l0_ncontrib = 0;
+    // upper pass (rows of levels >= 1 with entries)
+    int64_t n_up = 0;
+    int32_t *up_ptr = nullptr, *up_col = nullptr;
+    float *up_val = nullptr;
+    int32_t *up_cptr = nullptr, *up_cidx = nullptr;
+    int64_t up_nnz = 0, up_ncontrib = 0;
+    // chunk pass
+    int64_t n_chunks = 0, chunked_rows = 0;
+    int32_t *ch_ptr = nullptr, *ch_col = nullptr;
+    float *ch_val = nullptr;
+    int64_t ch_nnz = 0;
+    // permutation pi_0^{-1}
+    int32_t *vop0 = nullptr;
+
+    int64_t s_rows = 0;  // partial-row buffer rows = n_up + n_chunks
+    // distinct X rows each pass reads (algorithmic byte model)
+    int64_t distinct_l0 = 0, distinct_up = 0, distinct_ch = 0;
+
+    std::vector<void *> allocs;
+    int64_t footprint = 0;
+
+    bool prof = false;
+    std::vector<ProfRec> prof_recs;
+    std::vector<hipEvent_t> ev_pool;
+};
+
+arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out);
+void plan_destroy(Plan *p);
+
+struct OpState {
+    const void *x;
+    void *y;
+    int64_t k, ldx, ldy;
+    int dtype;
+    const float *x_scale;
+    const double *x_inv_norm;
+    const float *x_maxabs;
+    float *y_scale;
+    float *y_maxabs;
+    double *y_norm;
+    double *y_inv_norm;
+};
+
+int64_t elem_size(int dtype);
+int tile_width(int64_t k);
+size_t op_workspace(const Plan &p, int64_t k, int dtype);
+// Enqueue one product for one operand; `ws` holds op_workspace bytes.
+arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s);
+int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype);
+
+arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                         const float *x, float *y, int64_t k, int64_t ld, double *ws,
+                         double *norms, hipStream_t s);
+size_t plain_csr_workspace(int64_t n, int64_t k);
+
+}  // namespace arrow

@@ -1,0 +1,152 @@
+"""Host side of libarrow on the CPU: decomposition parity with the oracle's
+LA-Decompose (bit-exact: integer / index work), validity at larger sizes,
+save/load, error paths and the exported C-ABI symbols."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import decomp as D
+from oracle import spmm as S
+
+A_ = pytest.importorskip("paper_2402_19364_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_decompose(A, b, seed=0, la=A_.LA_RANDOM_FOREST, max_levels=0):
+    return A_.Decomposition.from_matrix(A, b, seed=seed, la=la, max_levels=max_levels)
+
+
+def _assert_same(levels_lib, levels_ref):
+    assert len(levels_lib) == len(levels_ref)
+    for L, R in zip(levels_lib, levels_ref):
+        assert L["n_i"] == R["n_i"]
+        assert np.array_equal(L["vop"], R["vop"])
+        assert np.array_equal(L["row_ptr"], R["row_ptr"])
+        assert np.array_equal(L["col"], R["col"])
+        assert np.array_equal(L["val"].view(np.uint32), np.asarray(R["val"], np.float32).view(np.uint32))
+
+
+def _small_graphs():
+    gs = []
+    for seed in range(5):
+        gs.append(W.random_graph(60, 0.08, seed, diagonal=seed % 2 == 0))
+    gs.append(W.make_matrix("grid2d", 12, "uniform", 0, 1))
+    gs.append(W.make_matrix("grid3d", 5, "sym_laplacian", 0, 1))
+    gs.append(W.make_matrix("rmat", 9, "row_normalized", 3, 4, 8))
+    gs.append(W.from_edges(40, [(0, i) for i in range(1, 40)]))             # star
+    gs.append(W.from_edges(50, [(i, i + 1) for i in range(49)]))            # path
+    gs.append(W.from_edges(30, [], diagonal=True))                          # diagonal only
+    gs.append(W.from_edges(17, []))                                         # empty
+    gs.append(W.from_edges(20, [(0, 5), (5, 0), (3, 9)], symmetric=False))  # non-symmetric
+    return gs
+
+
+@pytest.mark.parametrize("la", [A_.LA_RANDOM_FOREST, A_.LA_IDENTITY])
+@pytest.mark.parametrize("b", [2, 3, 8])
+def test_decomposition_matches_oracle_bitwise(la, b):
+    for i, A in enumerate(_small_graphs()):
+        ref = D.la_decompose(A, b, seed=17 + i, la="random_forest" if la == 0 else "identity")
+        got = _lib_decompose(A, b, seed=17 + i, la=la).levels()
+        _assert_same(got, ref)
+
+
+def test_decomposition_matches_oracle_medium_rmat():
+    A = W.make_matrix("rmat", 12, "row_normalized", 21, 22, 16)
+    ref = D.la_decompose(A, 64, seed=5)
+    got = _lib_decompose(A, 64, seed=5).levels()
+    _assert_same(got, ref)
+    assert len(got) >= 2
+
+
+@pytest.mark.parametrize("cfg", ["grid64"])
+def test_config_small_decomposition(cfg):
+    w = W.WORKLOADS[cfg]
+    A = W.workload_matrix(w)
+    d = _lib_decompose(A, w.b, seed=w.seeds["decompose"])
+    ref = D.la_decompose(A, w.b, seed=w.seeds["decompose"])
+    _assert_same(d.levels(), ref)
+    D.validate(A, d.levels(), w.b)
+
+
+def test_large_decompositions_are_valid():
+    A = W.make_matrix("grid2d", 256, "sym_laplacian", 0, 0)
+    for la in (A_.LA_RANDOM_FOREST, A_.LA_IDENTITY):
+        lv = _lib_decompose(A, 256, seed=4, la=la).levels()
+        D.validate(A, lv, 256)
+    lv = _lib_decompose(A, 256, la=A_.LA_IDENTITY).levels()
+    assert len(lv) == 1  # natural-order grid, bandwidth = side = b
+    R = W.make_matrix("rmat", 15, "row_normalized", 9, 10, 16)
+    lv = _lib_decompose(R, 256, seed=1).levels()
+    D.validate(R, lv, 256)
+    X = np.random.default_rng(0).standard_normal((R.n, 4))
+    # Eq. (1) on the library's levels equals A X (only at small n: dense per level)
+    small = W.make_matrix("rmat", 8, "row_normalized", 1, 2, 8)
+    lv = _lib_decompose(small, 4, seed=3).levels()
+    Xs = np.random.default_rng(1).standard_normal((small.n, 3))
+    assert np.allclose(D.product_via_levels(lv, small.n, Xs), S.csr_spmm(small, Xs),
+                       rtol=1e-12, atol=1e-12)
+    del X
+
+
+def test_determinism_and_save_load(tmp_path):
+    A = W.make_matrix("rmat", 11, "row_normalized", 1, 2, 16)
+    d1 = _lib_decompose(A, 32, seed=9)
+    d2 = _lib_decompose(A, 32, seed=9)
+    _assert_same(d1.levels(), d2.levels())
+    p = str(tmp_path / "d.arrow")
+    d1.save(p)
+    d3 = A_.Decomposition.load(p)
+    _assert_same(d3.levels(), d1.levels())
+    assert d3.info()["nnz"] == A.nnz
+    raw = bytearray(open(p, "rb").read())
+    raw[100] ^= 0xFF
+    open(p, "wb").write(bytes(raw))
+    with pytest.raises(A_.ArrowError) as e:
+        A_.Decomposition.load(p)
+    assert e.value.status == A_.ERR_IO
+    with pytest.raises(A_.ArrowError):
+        A_.Decomposition.load(str(tmp_path / "missing"))
+
+
+def test_error_paths():
+    A = W.random_graph(20, 0.2, 1)
+    with pytest.raises(A_.ArrowError) as e:
+        _lib_decompose(A, 1)
+    assert e.value.status == A_.ERR_INVALID_ARG
+    bad = W.CSR(A.n, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    bad.col[bad.row_ptr[3]] = 99  # out of range
+    with pytest.raises(A_.ArrowError):
+        _lib_decompose(bad, 4)
+    bad = W.CSR(A.n, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    r = int(np.argmax(np.diff(bad.row_ptr)))
+    s = bad.row_ptr[r]
+    bad.col[s], bad.col[s + 1] = bad.col[s + 1], bad.col[s]  # unsorted row
+    with pytest.raises(A_.ArrowError):
+        _lib_decompose(bad, 4)
+    bad = W.CSR(A.n, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    bad.row_ptr[5] = bad.row_ptr[6] + 1  # decreasing
+    with pytest.raises(A_.ArrowError):
+        _lib_decompose(bad, 4)
+    R = W.make_matrix("rmat", 10, "row_normalized", 1, 2, 16)
+    with pytest.raises(A_.ArrowError) as e:
+        _lib_decompose(R, 2, max_levels=1)
+    assert e.value.status == A_.ERR_UNSUPPORTED
+    msg = A_.lib().arrow_last_error().decode()
+    assert "max_levels" in msg
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "arrow.h")).read()
+    declared = set(re.findall(r"\b(arrow_[a-z0-9_]+)\s*\(", hdr))
+    out = subprocess.run(["nm", "-D", "--defined-only", A_.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = declared - exported
+    assert not missing, missing
+    for name in declared:
+        getattr(A_.lib(), name)
+    assert A_.version() == "1.0.0"
