@@ -1,0 +1,297 @@
+"""Benchmark of the iterated arrow-decomposition SpMM on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid2048]
+
+One step = one job of the hot path on a synthetic workload already resident in
+HBM: permute X into level-0 order, T products Y_t = A X_t with per-column FP64
+renormalisation folded into the next product, permute the result back.  The
+decomposition (host) and the plan upload happen once, before timing.
+
+Prints one JSON line: whole-step algorithmic GB/s (value), its fraction of the
+8 TB/s HBM peak, per-iteration p50/p99 latency, the plain CSR SpMM baseline on
+the same GPU (as-generated order, same dtype/k/norm epilogue), the roofline of
+the dominant kernel (level-0 pass; its duration measured with HIP events around
+every launch on the launch stream) and the FP64 oracle timed on host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "arrow-SpMM GB/s (% HBM peak) vs plain CSR on same GPU; p50/p99 latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_2402_19364_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, dtype: str, la: str):
+    """HBM bytes per level-0 launch from the committed rocprofv3 counter runs,
+    or None when absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = data.get(f"{workload}/{dtype}/{la}")
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(M, X0, bytes_per_iter: float, budget_s: float):
+    """The FP64 oracle (test infrastructure) timed on the host cores."""
+    from oracle import spmm as S
+    threads = S.num_threads()
+    X = X0.astype(np.float64)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        Y = S.csr_spmm(M, X)
+        _, X = S.renormalize(Y)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s or len(times) >= 20:
+            break
+    t = float(np.median(times))
+    return {"value": round(bytes_per_iter / t / 1e9, 3), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(times)} FP64 CSR iterations (product + column renormalisation) "
+                      f"of the same workload, median {t * 1e3:.1f} ms/iteration, rated on "
+                      f"the same algorithmic bytes per iteration as the GPU line"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid2048")
+    ap.add_argument("--dtype", default=None, help="f32 | bf16 | f16 | f8e4m3")
+    ap.add_argument("--la", default="random_forest", choices=["random_forest", "identity"])
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-csr", action="store_true", help="skip the plain CSR baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run the streaming copy kernel N times over 1 GiB")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2402_19364_amd as arrow
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    if args.copy_calib:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.copy_calib):
+            arrow.copy(a, b, nbytes)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.copy_calib
+        print(json.dumps({"copy_bytes": nbytes, "launches": args.copy_calib,
+                          "ms_per_copy": ms, "GBps": 2 * nbytes / ms / 1e6}), flush=True)
+        return
+
+    w = W.WORKLOADS[args.workload]
+    dtype = args.dtype or w.dtypes[0]
+    T = args.iters or w.iters
+    k = args.k or w.k
+    la = arrow.LA_RANDOM_FOREST if args.la == "random_forest" else arrow.LA_IDENTITY
+
+    t0 = time.perf_counter()
+    M = W.workload_matrix(w)
+    t_gen = time.perf_counter() - t0
+    log(f"[bench] {w.describe()} n={M.n} nnz={M.nnz} generated in {t_gen:.1f}s")
+    d = arrow.Decomposition.from_matrix(M, w.b, seed=w.seeds["decompose"], la=la)
+    dinfo = d.info()
+    log(f"[bench] decomposition: {dinfo['levels']} levels in {dinfo['seconds']:.1f}s")
+    t0 = time.perf_counter()
+    plan = arrow.Plan(d)
+    t_plan = time.perf_counter() - t0
+    pinfo = plan.info()
+    del d
+    log(f"[bench] plan: {pinfo}")
+
+    X0 = W.features(M.n, k, w.seeds["x"])
+    x = torch.from_numpy(X0).to(dev)
+    out = torch.empty_like(x)
+    scaled = dtype in ("f16", "f8e4m3")
+    xp = plan.empty(k, dtype)
+    bufs = [plan.empty(k, dtype), plan.empty(k, dtype)]
+    ws = plan.workspace(plan.workspace_size(k, dtype))
+    x_scale = torch.ones(k, dtype=torch.float32, device=dev)
+    x_max = torch.zeros(k, dtype=torch.float32, device=dev)
+    inv = [torch.zeros(k, dtype=torch.float64, device=dev) for _ in range(2)]
+    mx = [torch.zeros(k, dtype=torch.float32, device=dev) for _ in range(2)]
+    scl = [torch.ones(k, dtype=torch.float32, device=dev) for _ in range(2)]
+    norms = torch.zeros((T, k), dtype=torch.float64, device=dev)
+
+    def step(events=None):
+        plan.permute_in(x, xp, dtype, x_scale=x_scale if scaled else None,
+                        x_maxabs=x_max if scaled else None)
+        cur, cur_scale, cur_max = xp, (x_scale if scaled else None), (x_max if scaled else None)
+        if events is not None:
+            events[0].record()
+        for t in range(T):
+            y = bufs[t % 2]
+            op = arrow.operand(cur, y, dtype, x_scale=cur_scale,
+                               x_inv_norm=inv[(t - 1) % 2] if t > 0 else None,
+                               x_maxabs=cur_max,
+                               y_scale=scl[t % 2] if scaled else None,
+                               y_maxabs=mx[t % 2] if scaled else None,
+                               y_norm=norms[t], y_inv_norm=inv[t % 2])
+            plan.spmm([op], ws)
+            if events is not None:
+                events[t + 1].record()
+            cur, cur_scale, cur_max = y, (scl[t % 2] if scaled else None), \
+                (mx[t % 2] if scaled else None)
+        plan.permute_out(cur, out, dtype, x_scale=cur_scale, col_factor=inv[(T - 1) % 2])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    it_events = [[torch.cuda.Event(enable_timing=True) for _ in range(T + 1)]
+                 for _ in range(args.steps)]
+    e_start = torch.cuda.Event(enable_timing=True)
+    e_stop = torch.cuda.Event(enable_timing=True)
+    plan.profile(True)
+    torch.cuda.synchronize()
+    e_start.record()
+    for s in range(args.steps):
+        step(it_events[s])
+    e_stop.record()
+    torch.cuda.synchronize()
+    plan.profile(False)
+    total_ms = e_start.elapsed_time(e_stop)
+    ms_step = total_ms / args.steps
+    iter_ms = np.array([ev[t].elapsed_time(ev[t + 1]) for ev in it_events for t in range(T)])
+
+    kb = {kid: plan.kernel_bytes(kid, k, dtype) for kid in arrow.KERNEL_NAMES}
+    bytes_iter = sum(kb[kid] for kid in (arrow.KERNEL_CHUNKS, arrow.KERNEL_UPPER,
+                                         arrow.KERNEL_LEVEL0, arrow.KERNEL_NORM))
+    bytes_step = T * bytes_iter + 2 * kb[arrow.KERNEL_PERMUTE]
+    gbs = bytes_step / (ms_step * 1e-3) / 1e9
+    flops_iter = 2.0 * M.nnz * k
+    per_kernel = {}
+    for kid, name in arrow.KERNEL_NAMES.items():
+        launches, ms = plan.profile_query(kid)
+        if launches:
+            per_kernel[name] = {"launches": launches, "avg_us": round(ms / launches * 1e3, 2),
+                                "alg_bytes": kb[kid],
+                                "GBps": round(kb[kid] / (ms / launches * 1e-3) / 1e9, 1)}
+    dom = max((v for v in per_kernel.values()), key=lambda v: v["avg_us"] * v["launches"])
+    dom_name = [n for n, v in per_kernel.items() if v is dom][0]
+    lvl = per_kernel["level0"]
+    achieved = lvl["alg_bytes"] / (lvl["avg_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(args.workload, dtype, args.la)
+
+    # plain CSR baseline: as-generated order, same k and dtype (f32), FP64 norm epilogue
+    csr = None
+    if not args.no_csr and dtype == "f32":
+        rp = torch.from_numpy(M.row_ptr.astype(np.int32)).to(dev)
+        col = torch.from_numpy(M.col).to(dev)
+        val = torch.from_numpy(M.val).to(dev)
+        cx = x.clone()
+        cy = torch.empty_like(cx)
+        cws = torch.empty(arrow.csr_workspace_size(M.n, k), dtype=torch.uint8, device=dev)
+        cn = torch.empty(k, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            arrow.csr_spmm(M.n, rp, col, val, cx, cy, cws.view(torch.float64), cn)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T + 1)]
+        evs[0].record()
+        for t in range(2 * T):
+            arrow.csr_spmm(M.n, rp, col, val, cx if t % 2 == 0 else cy,
+                           cy if t % 2 == 0 else cx, cws.view(torch.float64), cn)
+            evs[t + 1].record()
+        torch.cuda.synchronize()
+        c_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(2 * T)])
+        b_min = M.nnz * 8 + 4 * (M.n + 1) + M.n * k * 8
+        csr = {"kernel": "hand-written HIP CSR (as-generated order, int32 indices)",
+               "iter_ms_p50": round(float(np.median(c_ms)), 4),
+               "iter_ms_p99": round(float(np.percentile(c_ms, 99)), 4),
+               "GBps_on_Bmin": round(b_min / (np.median(c_ms) * 1e-3) / 1e9, 1)}
+        del cx, cy
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the FP64 oracle on the host cores")
+        cpu = cpu_baseline(M, X0, bytes_iter, args.cpu_budget)
+
+    p50 = float(np.median(iter_ms))
+    line = {
+        "metric": METRIC,
+        "value": round(gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": w.describe(), "n": M.n,
+                   "nnz": M.nnz, "k": k, "b": w.b, "iterations": T,
+                   "linear_arrangement": args.la, "levels": pinfo["levels"]},
+        "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+        "iter_ms_p50": round(p50, 4),
+        "iter_ms_p99": round(float(np.percentile(iter_ms, 99)), 4),
+        "iter_GFLOPs": round(flops_iter / (p50 * 1e-3) / 1e9, 1),
+        "alg_bytes_per_iter": bytes_iter,
+        "kernels": per_kernel,
+        "csr_baseline": csr,
+        "speedup_vs_csr": (round(csr["iter_ms_p50"] / p50, 3) if csr else None),
+        "roofline": {"kernel": "level0", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "dominant": dom_name},
+        "cpu_baseline": cpu,
+        "setup_s": {"generate": round(t_gen, 2), "decompose": round(dinfo["seconds"], 2),
+                    "plan_upload": round(t_plan, 2)},
+        "kernel_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

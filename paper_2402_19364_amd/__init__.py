@@ -135,6 +135,13 @@ def _tptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _rows(t, name: str) -> int:
+    """Row stride of a row-major 2-D tensor whose columns are contiguous."""
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must be a 2-D tensor with contiguous columns")
+    return t.stride(0)
+
+
 def _stream_handle(stream=None) -> Optional[int]:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -287,17 +294,21 @@ class Plan:
     def permute_in(self, x, out, dtype="f32", x_scale=None, x_maxabs=None, stream=None):
         """out = P_{pi_0}^T x converted to `dtype` (x: FP32 original order)."""
         k = x.shape[1]
-        _check(_load().arrow_permute_in(self._h, _tptr(x), x.stride(0), _tptr(out),
-                                        out.stride(0), _dtype_code(dtype), k, _tptr(x_scale),
+        if out.shape[1] != k:
+            raise ValueError("x and out must have the same number of columns")
+        _check(_load().arrow_permute_in(self._h, _tptr(x), _rows(x, "x"), _tptr(out),
+                                        _rows(out, "out"), _dtype_code(dtype), k, _tptr(x_scale),
                                         _tptr(x_maxabs), _stream_handle(stream)))
         return out
 
     def permute_out(self, y_plan, out, dtype="f32", x_scale=None, col_factor=None, stream=None):
         """out (FP32, original order) = P_{pi_0} y_plan * scale * factor."""
         k = y_plan.shape[1]
-        _check(_load().arrow_permute_out(self._h, _tptr(y_plan), y_plan.stride(0),
+        if out.shape[1] != k:
+            raise ValueError("y_plan and out must have the same number of columns")
+        _check(_load().arrow_permute_out(self._h, _tptr(y_plan), _rows(y_plan, "y_plan"),
                                          _dtype_code(dtype), k, _tptr(x_scale),
-                                         _tptr(col_factor), _tptr(out), out.stride(0),
+                                         _tptr(col_factor), _tptr(out), _rows(out, "out"),
                                          _stream_handle(stream)))
         return out
 
@@ -310,9 +321,12 @@ class Plan:
     def iterate(self, x, y, iters: int, dtype="f32", renorm: bool = True, norms=None,
                 x_scale=None, y_scale=None, workspace=None, stream=None):
         k = x.shape[1]
+        ld = _rows(x, "x")
+        if tuple(y.shape) != tuple(x.shape) or _rows(y, "y") != ld:
+            raise ValueError("x and y must have the same shape and row stride")
         if workspace is None:
             workspace = self.workspace(self.iterate_workspace_size(k, dtype))
-        _check(_load().arrow_spmm_iterate(self._h, _tptr(x), _tptr(y), k, x.stride(0),
+        _check(_load().arrow_spmm_iterate(self._h, _tptr(x), _tptr(y), k, ld,
                                           _dtype_code(dtype), _tptr(x_scale), _tptr(y_scale),
                                           iters, ITER_RENORM if renorm else 0, _tptr(norms),
                                           _tptr(workspace),
@@ -344,7 +358,9 @@ class Plan:
 
 def operand(x, y, dtype="f32", x_scale=None, x_inv_norm=None, x_maxabs=None, y_scale=None,
             y_maxabs=None, y_norm=None, y_inv_norm=None) -> Operand:
-    return Operand(_tptr(x), _tptr(y), x.shape[1], x.stride(0), y.stride(0),
+    if tuple(x.shape) != tuple(y.shape):
+        raise ValueError("x and y must have the same shape")
+    return Operand(_tptr(x), _tptr(y), x.shape[1], _rows(x, "x"), _rows(y, "y"),
                    _dtype_code(dtype), 0, _tptr(x_scale), _tptr(x_inv_norm), _tptr(x_maxabs),
                    _tptr(y_scale), _tptr(y_maxabs), _tptr(y_norm), _tptr(y_inv_norm))
 
@@ -357,8 +373,11 @@ def csr_workspace_size(n: int, k: int) -> int:
 
 def csr_spmm(n: int, row_ptr, col, val, x, y, sumsq_ws=None, norms=None, stream=None):
     """Plain CSR baseline on the device (int32 row_ptr / col, FP32 values)."""
+    ld = _rows(x, "x")
+    if tuple(y.shape) != tuple(x.shape) or _rows(y, "y") != ld:
+        raise ValueError("x and y must have the same shape and row stride")
     _check(_load().arrow_csr_spmm(n, _tptr(row_ptr), _tptr(col), _tptr(val), _tptr(x), _tptr(y),
-                                  x.shape[1], x.stride(0), _tptr(sumsq_ws), _tptr(norms),
+                                  x.shape[1], ld, _tptr(sumsq_ws), _tptr(norms),
                                   _stream_handle(stream)))
     return y
 

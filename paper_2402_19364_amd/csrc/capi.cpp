@@ -481,10 +481,15 @@ arrow_status_t arrow_spmm_iterate(arrow_plan_t p, const void *x, void *y, int64_
     const bool sc = scaled(dtype);
     for (int32_t t = 0; t < iters; ++t) {
         arrow::OpState op{};
-        op.x = t == 0 ? x : ((iters - t) % 2 == 0 ? y : z);
-        op.y = (iters - 1 - t) % 2 == 0 ? y : z;
+        // outputs alternate so that the last one lands in y; the scratch
+        // buffer z is compact (row stride k)
+        const bool x_is_z = t > 0 && (iters - t) % 2 != 0;
+        const bool y_is_z = (iters - 1 - t) % 2 != 0;
+        op.x = t == 0 ? x : (x_is_z ? z : y);
+        op.y = y_is_z ? z : y;
         op.k = k;
-        op.ldx = op.ldy = ld;
+        op.ldx = x_is_z ? k : ld;
+        op.ldy = y_is_z ? k : ld;
         op.dtype = dtype;
         op.x_scale = t == 0 ? x_scale : (sc ? scl[(t - 1) % 2] : nullptr);
         op.x_inv_norm = (t == 0 || !renorm) ? nullptr : inv[(t - 1) % 2];

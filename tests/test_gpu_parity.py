@@ -69,11 +69,16 @@ def _check_trajectory(M, b, k, T, seed_x=7, la=0, decomp_seed=1, ld=None, label=
         prev, pnu = y, nu
     say(f"[parity] {label} ok: worst teacher-forced {worst_tf:.2e} free-running {worst_fr:.2e}")
     # arrow_spmm_iterate runs the same kernels: bitwise equal final product
-    y_it = plan.empty(k)
+    y_it = torch.zeros((M.n, ldx), dtype=torch.float32, device="cuda")[:, :k]
     nrm = torch.zeros(T * k, dtype=torch.float64, device="cuda")
     plan.iterate(x_plan, y_it, T, norms=nrm)
     torch.cuda.synchronize()
     assert torch.equal(y_it, ys[-1])
+    for T2 in (1, 2):  # both parities of the ping-pong through the compact scratch buffer
+        y2 = torch.zeros((M.n, ldx), dtype=torch.float32, device="cuda")[:, :k]
+        plan.iterate(x_plan, y2, T2)
+        torch.cuda.synchronize()
+        assert torch.equal(y2, ys[T2 - 1]), T2
     assert torch.equal(nrm.view(T, k), torch.stack(norms))
     # permute_out with the last normalisation gives X_T in the original order
     out = torch.empty((M.n, k), dtype=torch.float32, device="cuda")

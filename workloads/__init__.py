@@ -54,18 +54,25 @@ def _pattern_from_keys(n: int, keys: np.ndarray) -> tuple[np.ndarray, np.ndarray
     return row_ptr, col
 
 
+def _stencil_pattern(n: int, offsets, valid) -> tuple[np.ndarray, np.ndarray]:
+    """CSR of a stencil: row v holds v + off for every offset whose mask is set.
+    Offsets are ascending, so columns come out sorted without a sort."""
+    v = np.arange(n, dtype=np.int64)
+    cols = np.stack([v + off for off in offsets], axis=1)
+    mask = np.stack(valid, axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=row_ptr[1:])
+    return row_ptr, cols[mask].astype(np.int32)
+
+
 def grid2d_pattern(side: int, diagonal: bool = True) -> tuple[int, np.ndarray, np.ndarray]:
     """5-point stencil on a side x side grid, vertex id = y*side + x (natural order)."""
     n = side * side
     v = np.arange(n, dtype=np.int64)
     x = v % side
-    parts = []
-    if diagonal:
-        parts.append(v * n + v)
-    for dv, ok in ((-side, v >= side), (-1, x > 0), (1, x < side - 1), (side, v < n - side)):
-        u = v[ok]
-        parts.append(u * n + (u + dv))
-    row_ptr, col = _pattern_from_keys(n, np.concatenate(parts))
+    offs = [-side, -1, 0, 1, side]
+    valid = [v >= side, x > 0, np.full(n, diagonal), x < side - 1, v < n - side]
+    row_ptr, col = _stencil_pattern(n, offs, valid)
     return n, row_ptr, col
 
 
@@ -77,14 +84,10 @@ def grid3d_pattern(side: int, diagonal: bool = True) -> tuple[int, np.ndarray, n
     x = v % side
     y = (v // side) % side
     z = v // s2
-    parts = []
-    if diagonal:
-        parts.append(v * n + v)
-    for dv, ok in ((-s2, z > 0), (-side, y > 0), (-1, x > 0),
-                   (1, x < side - 1), (side, y < side - 1), (s2, z < side - 1)):
-        u = v[ok]
-        parts.append(u * n + (u + dv))
-    row_ptr, col = _pattern_from_keys(n, np.concatenate(parts))
+    offs = [-s2, -side, -1, 0, 1, side, s2]
+    valid = [z > 0, y > 0, x > 0, np.full(n, diagonal), x < side - 1, y < side - 1,
+             z < side - 1]
+    row_ptr, col = _stencil_pattern(n, offs, valid)
     return n, row_ptr, col
 
 
