@@ -10,12 +10,15 @@ namespace arrow {
 enum : int { kF32 = 0, kF16 = 1, kBF16 = 2, kF8E4M3 = 3 };
 enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
 constexpr int kNumXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
+constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
 
 // One row pass over a CSR-like set of rows.
 struct RowPass {
     int64_t nrows;
-    int32_t rows_per_block;
-    int32_t nblocks;
+    int32_t rows_per_block;  // <= kMaxBlockRows
+    int32_t blocks_per_wg;   // consecutive blocks walked by one workgroup
+    int32_t nwg;             // workgroups = ceil(blocks / blocks_per_wg)
     const int32_t *ptr;   // [nrows + 1] direct entry offsets
     const void *idx;      // uint16 codes (level-0 band/head) or int32 pi_0 columns
     const float *val;

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -211,6 +212,13 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 // row kernel
 // ---------------------------------------------------------------------------
 
+// Each workgroup walks `blocks_per_wg` consecutive blocks of rows_per_block
+// rows.  Per block it first stages the row pointers, the list pointers and up
+// to kStageEntries matrix entries into LDS with coalesced loads, so that the
+// per-row work only waits on the X-row gathers: a lane group reads up to 8
+// entries of its row from LDS and issues their 8 independent X-row loads
+// before accumulating.  Entries beyond the staged range (a block with more
+// entries than fit) are read from global memory.
 template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL>
 __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) {
     using F = Fmt<DT>;
@@ -218,16 +226,23 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     constexpr int LPR = KT / VEC;             // lanes per row
     constexpr int RPW = kWave / LPR;          // rows per wave and round
     constexpr int RPR = RPW * kWaves;         // rows per workgroup and round
+    constexpr int UNR = 8;                    // entries gathered per batch
     static_assert(LPR >= 1 && kWave % LPR == 0, "tile width");
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
+    using IdxT = typename std::conditional<CODE16, uint16_t, int32_t>::type;
 
-    const int blk = xcd_block(blockIdx.x, rp.nblocks);
-    const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
+    __shared__ int32_t s_ptr[kMaxBlockRows + 1];
+    __shared__ int32_t s_cptr[CONTRIB ? kMaxBlockRows + 1 : 1];
+    __shared__ IdxT s_idx[kStageEntries];
+    __shared__ float s_val[kStageEntries];
+
+    const int wg = xcd_block(blockIdx.x, gridDim.x);
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave;
+    const int wave = tid / kWave;
     const int g = lane / LPR;
     const int sub = lane % LPR;
-    const int64_t row0 = (int64_t)blk * rp.rows_per_block;
-    const int64_t row1 = row0 + rp.rows_per_block < rp.nrows ? row0 + rp.rows_per_block : rp.nrows;
+    const IdxT *gidx = reinterpret_cast<const IdxT *>(rp.idx);
 
     const char *xb = reinterpret_cast<const char *>(t.x) + (int64_t)sub * 16;
     const int64_t xstride = t.ldx * kElem;
@@ -257,83 +272,112 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
             cmax[i] = 0.0f;
         }
         if constexpr (F::kScaled) {
-            if (blk == 0 && wave == 0 && g == 0 && t.y_scale) {
+            if (wg == 0 && wave == 0 && g == 0 && t.y_scale) {
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) t.y_scale[sub * VEC + i] = cscale[i];
             }
         }
     }
 
-    for (int64_t r = row0 + wave * RPW + g; r < row1; r += RPR) {
-        float acc[VEC];
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-        int e = rp.ptr[r];
-        const int e1 = rp.ptr[r + 1];
-        const int rb = (int)r - rp.b;  // column of code 0 (band start) for 16-bit codes
-        auto column = [&](int ee) -> int64_t {
-            if constexpr (CODE16) {
-                const int code = reinterpret_cast<const uint16_t *>(rp.idx)[ee];
-                return code <= 2 * rp.b ? (int64_t)(rb + code) : (int64_t)(code - 2 * rp.b - 1);
-            } else {
-                return reinterpret_cast<const int32_t *>(rp.idx)[ee];
-            }
-        };
-        for (; e + 4 <= e1; e += 4) {
-            int64_t c[4];
-            float a[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                c[u] = column(e + u);
-                a[u] = rp.val[e + u];
-            }
-            float xv[4][VEC];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) F::load(xb + c[u] * xstride, xv[u]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[i] = fmaf(a[u], xv[u][i], acc[i]);
+    for (int bi = 0; bi < rp.blocks_per_wg; ++bi) {
+        const int64_t row0 = ((int64_t)wg * rp.blocks_per_wg + bi) * rp.rows_per_block;
+        if (row0 >= rp.nrows) break;
+        const int nr = (int)(row0 + rp.rows_per_block < rp.nrows ? rp.rows_per_block
+                                                                  : rp.nrows - row0);
+        __syncthreads();  // the previous block is done with the staged data
+        for (int i = tid; i <= nr; i += kBlockThreads) {
+            s_ptr[i] = rp.ptr[row0 + i];
+            if constexpr (CONTRIB) s_cptr[i] = rp.cptr[row0 + i];
         }
-        for (; e < e1; ++e) {
-            const int64_t c = column(e);
-            const float a = rp.val[e];
-            float xv[VEC];
-            F::load(xb + c * xstride, xv);
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] = fmaf(a, xv[i], acc[i]);
+        __syncthreads();
+        const int e0 = s_ptr[0];
+        const int ne = s_ptr[nr] - e0;
+        const int ns = ne < kStageEntries ? ne : kStageEntries;
+        for (int i = tid; i < ns; i += kBlockThreads) {
+            s_idx[i] = gidx[e0 + i];
+            s_val[i] = rp.val[e0 + i];
         }
-        if constexpr (CONTRIB) {
-            const int c0 = rp.cptr[r], c1 = rp.cptr[r + 1];
-            for (int c = c0; c < c1; ++c) {
-                const float *srow = t.s + (int64_t)rp.cidx[c] * t.lds + sub * VEC;
+        __syncthreads();
+
+        for (int rl = wave * RPW + g; rl < nr; rl += RPR) {
+            const int64_t r = row0 + rl;
+            float acc[VEC];
 #pragma unroll
-                for (int i = 0; i < VEC; i += 4) {
-                    float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
-                    acc[i] += s4.x;
-                    acc[i + 1] += s4.y;
-                    acc[i + 2] += s4.z;
-                    acc[i + 3] += s4.w;
+            for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+            const int a = s_ptr[rl] - e0, b = s_ptr[rl + 1] - e0;
+            const int rb = (int)r - rp.b;  // column of code 0 (band start) for 16-bit codes
+            for (int e = a; e < b; e += UNR) {
+                float av[UNR];
+                int64_t cv[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    av[u] = 0.0f;
+                    cv[u] = 0;
+                    const int ee = e + u;
+                    if (ee < b) {
+                        IdxT code;
+                        if (ee < ns) {
+                            code = s_idx[ee];
+                            av[u] = s_val[ee];
+                        } else {
+                            code = gidx[e0 + ee];
+                            av[u] = rp.val[e0 + ee];
+                        }
+                        if constexpr (CODE16) {
+                            const int c = code;
+                            cv[u] = c <= 2 * rp.b ? (int64_t)(rb + c) : (int64_t)(c - 2 * rp.b - 1);
+                        } else {
+                            cv[u] = code;
+                        }
+                    }
+                }
+                float xv[UNR][VEC];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    if (e + u < b) {
+                        F::load(xb + cv[u] * xstride, xv[u]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) xv[u][i] = 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) acc[i] = fmaf(av[u], xv[u][i], acc[i]);
+            }
+            if constexpr (CONTRIB) {
+                const int c0 = s_cptr[rl], c1 = s_cptr[rl + 1];
+                for (int c = c0; c < c1; ++c) {
+                    const float *srow = t.s + (int64_t)rp.cidx[c] * t.lds + sub * VEC;
+#pragma unroll
+                    for (int i = 0; i < VEC; i += 4) {
+                        float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
+                        acc[i] += s4.x;
+                        acc[i + 1] += s4.y;
+                        acc[i + 2] += s4.z;
+                        acc[i + 3] += s4.w;
+                    }
                 }
             }
-        }
-        if constexpr (FINAL) {
+            if constexpr (FINAL) {
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * fac[i] * cinv[i];
-            char *yp = reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
-            F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
+                for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * fac[i] * cinv[i];
+                char *yp = reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
+                F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-                const double v = (double)acc[i] * (double)cscale[i];
-                ssq[i] += v * v;
-                cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
+                for (int i = 0; i < VEC; ++i) {
+                    const double v = (double)acc[i] * (double)cscale[i];
+                    ssq[i] += v * v;
+                    cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
+                }
+            } else {
+                float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
+#pragma unroll
+                for (int i = 0; i < VEC; i += 4)
+                    *reinterpret_cast<float4 *>(sp + i) =
+                        make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
             }
-        } else {
-            float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
-#pragma unroll
-            for (int i = 0; i < VEC; i += 4)
-                *reinterpret_cast<float4 *>(sp + i) =
-                    make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
         }
     }
 
@@ -357,7 +401,7 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
             }
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < KT; j += kBlockThreads) {
+        for (int j = tid; j < KT; j += kBlockThreads) {
             double v = s_ssq[0][j];
             float m = s_max[0][j];
 #pragma unroll
@@ -365,8 +409,8 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                 v += s_ssq[w][j];
                 m = fmaxf(m, s_max[w][j]);
             }
-            if (t.part_sumsq) t.part_sumsq[(int64_t)j * t.part_ld + blk] = v;
-            if (t.part_max) t.part_max[(int64_t)j * t.part_ld + blk] = m;
+            if (t.part_sumsq) t.part_sumsq[(int64_t)j * t.part_ld + wg] = v;
+            if (t.part_max) t.part_max[(int64_t)j * t.part_ld + wg] = m;
         }
     }
 }
@@ -529,8 +573,8 @@ namespace {
 template <int KT, int DT>
 hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const Tile &t,
                         hipStream_t s) {
-    dim3 grid(rp.nblocks), block(dev::kBlockThreads);
-    if (rp.nblocks <= 0) return hipSuccess;
+    dim3 grid(rp.nwg), block(dev::kBlockThreads);
+    if (rp.nwg <= 0) return hipSuccess;
     switch (mode) {
     case kPassChunk:
         hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, false>), grid, block, 0, s, rp, t);

@@ -67,6 +67,21 @@ int tile_width(int64_t k) {
 
 static int64_t nblocks_of(int64_t rows, int64_t rpb) { return (rows + rpb - 1) / rpb; }
 
+// Workgroups of a pass over `rows` rows (blocks of rpb rows, bpw blocks each).
+static int64_t nwg_of(int64_t rows, int64_t rpb, int64_t bpw) {
+    return nblocks_of(nblocks_of(rows, rpb), bpw);
+}
+
+static void set_geometry(RowPass &rp, int64_t rows, int rpb, int bpw) {
+    rp.nrows = rows;
+    rp.rows_per_block = rpb;
+    rp.blocks_per_wg = bpw;
+    rp.nwg = (int32_t)nwg_of(rows, rpb, bpw);
+}
+
+// Partial slots of the final pass (one per workgroup of the level-0 pass).
+static int64_t final_parts(int64_t n) { return nwg_of(n, kRowsPerBlock, kBlocksPerWg); }
+
 arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out) {
     out = nullptr;
     Plan *pp = new (std::nothrow) Plan();
@@ -270,7 +285,7 @@ void plan_destroy(Plan *p) {
 
 size_t op_workspace(const Plan &p, int64_t k, int dtype) {
     (void)dtype;
-    const int64_t nb = nblocks_of(p.n, kRowsPerBlock);
+    const int64_t nb = final_parts(p.n);
     return align256((size_t)p.s_rows * k * 4) + align256((size_t)k * nb * 8) +
            align256((size_t)k * nb * 4);
 }
@@ -323,7 +338,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     if (n == 0) return ARROW_OK;
     const int kt = tile_width(k);
     const int64_t es = elem_size(op.dtype);
-    const int64_t nb = nblocks_of(n, kRowsPerBlock);
+    const int64_t nb = final_parts(n);
     char *w = static_cast<char *>(ws);
     float *sbuf = reinterpret_cast<float *>(w);
     w += align256((size_t)p.s_rows * k * 4);
@@ -332,9 +347,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     float *pmax = reinterpret_cast<float *>(w);
 
     RowPass ch{};
-    ch.nrows = p.n_chunks;
-    ch.rows_per_block = rows_per_round(kt, op.dtype);
-    ch.nblocks = (int32_t)nblocks_of(p.n_chunks, ch.rows_per_block);
+    set_geometry(ch, p.n_chunks, kChunksPerBlock, 1);
     ch.ptr = p.ch_ptr;
     ch.idx = p.ch_col;
     ch.val = p.ch_val;
@@ -342,9 +355,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     ch.out_row0 = (int32_t)p.n_up;
 
     RowPass upp{};
-    upp.nrows = p.n_up;
-    upp.rows_per_block = kRowsPerBlock;
-    upp.nblocks = (int32_t)nblocks_of(p.n_up, kRowsPerBlock);
+    set_geometry(upp, p.n_up, kRowsPerBlock, kBlocksPerWg);
     upp.ptr = p.up_ptr;
     upp.idx = p.up_col;
     upp.val = p.up_val;
@@ -354,9 +365,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.out_row0 = 0;
 
     RowPass l0{};
-    l0.nrows = n;
-    l0.rows_per_block = kRowsPerBlock;
-    l0.nblocks = (int32_t)nb;
+    set_geometry(l0, n, kRowsPerBlock, kBlocksPerWg);
     l0.ptr = p.l0_ptr;
     l0.idx = p.l0_idx;
     l0.val = p.l0_val;
@@ -411,7 +420,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
 
 int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
     const int64_t sx = elem_size(dtype);
-    const int64_t nb = nblocks_of(p.n, kRowsPerBlock);
+    const int64_t nb = final_parts(p.n);
     const bool scaled = dtype == kF16 || dtype == kF8E4M3;
     switch (kernel) {
     case ARROW_KERNEL_CHUNKS:
@@ -435,7 +444,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
 }
 
 size_t plain_csr_workspace(int64_t n, int64_t k) {
-    const int64_t nb = nblocks_of(n, kRowsPerBlock);
+    const int64_t nb = final_parts(n);
     return align256((size_t)k * nb * 8);
 }
 
@@ -444,11 +453,9 @@ arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, 
                          double *norms, hipStream_t s) {
     if (n == 0) return ARROW_OK;
     const int kt = tile_width(k);
-    const int64_t nb = nblocks_of(n, kRowsPerBlock);
+    const int64_t nb = final_parts(n);
     RowPass rp{};
-    rp.nrows = n;
-    rp.rows_per_block = kRowsPerBlock;
-    rp.nblocks = (int32_t)nb;
+    set_geometry(rp, n, kRowsPerBlock, kBlocksPerWg);
     rp.ptr = row_ptr;
     rp.idx = col;
     rp.val = val;

@@ -11,9 +11,11 @@
 
 namespace arrow {
 
-constexpr int kLongRow = 256;     // rows with more entries go through the chunk pass
-constexpr int kChunk = 256;       // entries per chunk
-constexpr int kRowsPerBlock = 512;
+constexpr int kLongRow = 128;     // rows with more entries go through the chunk pass
+constexpr int kChunk = 64;        // entries per chunk
+constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
+constexpr int kBlocksPerWg = 4;                    // blocks walked by one workgroup
+constexpr int kChunksPerBlock = kStageEntries / kChunk;
 
 struct ProfRec {
     int kernel;
