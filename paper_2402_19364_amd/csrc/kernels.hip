@@ -226,7 +226,8 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     constexpr int LPR = KT / VEC;             // lanes per row
     constexpr int RPW = kWave / LPR;          // rows per wave and round
     constexpr int RPR = RPW * kWaves;         // rows per workgroup and round
-    constexpr int UNR = 8;                    // entries gathered per batch
+    constexpr int UNR = 32 / VEC > 1 ? 32 / VEC : 2;  // entries gathered per row and batch
+    constexpr int P = kRowsPerLane;                    // rows per lane group and round
     static_assert(LPR >= 1 && kWave % LPR == 0, "tile width");
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     using IdxT = typename std::conditional<CODE16, uint16_t, int32_t>::type;
@@ -299,84 +300,111 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
         }
         __syncthreads();
 
-        for (int rl = wave * RPW + g; rl < nr; rl += RPR) {
-            const int64_t r = row0 + rl;
-            float acc[VEC];
+        // P rows per lane group and round: their gathers are issued together
+        for (int rl0 = wave * RPW + g; rl0 < nr; rl0 += RPR * P) {
+            float acc[P][VEC];
+            int a[P], len[P];
+            int maxlen = 0;
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-            const int a = s_ptr[rl] - e0, b = s_ptr[rl + 1] - e0;
-            const int rb = (int)r - rp.b;  // column of code 0 (band start) for 16-bit codes
-            for (int e = a; e < b; e += UNR) {
-                float av[UNR];
-                int64_t cv[UNR];
+            for (int p = 0; p < P; ++p) {
+                const int rl = rl0 + p * RPR;
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    av[u] = 0.0f;
-                    cv[u] = 0;
-                    const int ee = e + u;
-                    if (ee < b) {
-                        IdxT code;
-                        if (ee < ns) {
-                            code = s_idx[ee];
-                            av[u] = s_val[ee];
-                        } else {
-                            code = gidx[e0 + ee];
-                            av[u] = rp.val[e0 + ee];
-                        }
-                        if constexpr (CODE16) {
-                            const int c = code;
-                            cv[u] = c <= 2 * rp.b ? (int64_t)(rb + c) : (int64_t)(c - 2 * rp.b - 1);
-                        } else {
-                            cv[u] = code;
-                        }
-                    }
+                for (int i = 0; i < VEC; ++i) acc[p][i] = 0.0f;
+                a[p] = 0;
+                len[p] = 0;
+                if (rl < nr) {
+                    a[p] = s_ptr[rl] - e0;
+                    len[p] = s_ptr[rl + 1] - e0 - a[p];
                 }
-                float xv[UNR][VEC];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    if (e + u < b) {
-                        F::load(xb + cv[u] * xstride, xv[u]);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i) xv[u][i] = 0.0f;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < UNR; ++u)
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) acc[i] = fmaf(av[u], xv[u][i], acc[i]);
+                maxlen = len[p] > maxlen ? len[p] : maxlen;
             }
-            if constexpr (CONTRIB) {
-                const int c0 = s_cptr[rl], c1 = s_cptr[rl + 1];
-                for (int c = c0; c < c1; ++c) {
-                    const float *srow = t.s + (int64_t)rp.cidx[c] * t.lds + sub * VEC;
+            for (int e = 0; e < maxlen; e += UNR) {
+                float av[P][UNR];
+                int cv[P][UNR];  // X row numbers (the byte offset is formed at the load)
 #pragma unroll
-                    for (int i = 0; i < VEC; i += 4) {
-                        float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
-                        acc[i] += s4.x;
-                        acc[i + 1] += s4.y;
-                        acc[i + 2] += s4.z;
-                        acc[i + 3] += s4.w;
+                for (int p = 0; p < P; ++p) {
+                    const int rb = (int)(row0 + rl0 + p * RPR) - rp.b;  // band start (codes)
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        av[p][u] = 0.0f;
+                        cv[p][u] = 0;
+                        if (e + u < len[p]) {
+                            const int ee = a[p] + e + u;
+                            IdxT code;
+                            if (ee < ns) {
+                                code = s_idx[ee];
+                                av[p][u] = s_val[ee];
+                            } else {
+                                code = gidx[e0 + ee];
+                                av[p][u] = rp.val[e0 + ee];
+                            }
+                            if constexpr (CODE16) {
+                                const int c = code;
+                                cv[p][u] = c <= 2 * rp.b ? rb + c : c - 2 * rp.b - 1;
+                            } else {
+                                cv[p][u] = code;
+                            }
+                        }
                     }
                 }
+                float xv[P][UNR][VEC];
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        if (e + u < len[p]) {
+                            F::load(xb + (int64_t)cv[p][u] * xstride, xv[p][u]);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) xv[p][u][i] = 0.0f;
+                        }
+                    }
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i)
+                            acc[p][i] = fmaf(av[p][u], xv[p][u][i], acc[p][i]);
             }
-            if constexpr (FINAL) {
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * fac[i] * cinv[i];
-                char *yp = reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
-                F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
+            for (int p = 0; p < P; ++p) {
+                const int rl = rl0 + p * RPR;
+                if (rl >= nr) continue;
+                const int64_t r = row0 + rl;
+                if constexpr (CONTRIB) {
+                    const int c0 = s_cptr[rl], c1 = s_cptr[rl + 1];
+                    for (int c = c0; c < c1; ++c) {
+                        const float *srow = t.s + (int64_t)rp.cidx[c] * t.lds + sub * VEC;
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    const double v = (double)acc[i] * (double)cscale[i];
-                    ssq[i] += v * v;
-                    cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
+                        for (int i = 0; i < VEC; i += 4) {
+                            float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
+                            acc[p][i] += s4.x;
+                            acc[p][i + 1] += s4.y;
+                            acc[p][i + 2] += s4.z;
+                            acc[p][i + 3] += s4.w;
+                        }
+                    }
                 }
-            } else {
-                float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
+                if constexpr (FINAL) {
 #pragma unroll
-                for (int i = 0; i < VEC; i += 4)
-                    *reinterpret_cast<float4 *>(sp + i) =
-                        make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
+                    for (int i = 0; i < VEC; ++i) acc[p][i] = acc[p][i] * fac[i] * cinv[i];
+                    char *yp =
+                        reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
+                    F::store(yp, acc[p]);  // acc now holds the stored (rounded) codes as floats
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        const double v = (double)acc[p][i] * (double)cscale[i];
+                        ssq[i] += v * v;
+                        cmax[i] = fmaxf(cmax[i], fabsf(acc[p][i]));
+                    }
+                } else {
+                    float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
+#pragma unroll
+                    for (int i = 0; i < VEC; i += 4)
+                        *reinterpret_cast<float4 *>(sp + i) =
+                            make_float4(acc[p][i], acc[p][i + 1], acc[p][i + 2], acc[p][i + 3]);
+                }
             }
         }
     }
@@ -554,12 +582,21 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
         *reinterpret_cast<float4 *>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
 }
 
-// Streaming copy (HBM calibration): 16 bytes per lane and iteration.
+// Streaming copy (HBM calibration): every thread keeps 4 independent 16-byte
+// loads in flight before storing them.
 __global__ __launch_bounds__(kBlockThreads) void copy_kernel(const vu4 *src, vu4 *dst,
                                                              int64_t count) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * kBlockThreads)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    constexpr int D = 4;
+    const int64_t stride = (int64_t)gridDim.x * kBlockThreads;
+    int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+    for (; i + (D - 1) * stride < count; i += D * stride) {
+        vu4 v[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[d] = __builtin_nontemporal_load(src + i + d * stride);
+#pragma unroll
+        for (int d = 0; d < D; ++d) __builtin_nontemporal_store(v[d], dst + i + d * stride);
+    }
+    for (; i < count; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace dev
@@ -715,7 +752,7 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
     const int64_t count = bytes / 16;
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + dev::kBlockThreads - 1) / dev::kBlockThreads;
-    if (blocks > 256 * 32) blocks = 256 * 32;
+    if (blocks > 256 * 8) blocks = 256 * 8;
     hipLaunchKernelGGL(dev::copy_kernel, dim3((unsigned)blocks), dim3(dev::kBlockThreads), 0, s,
                        reinterpret_cast<const dev::vu4 *>(src), reinterpret_cast<dev::vu4 *>(dst), count);
     return hipGetLastError();
