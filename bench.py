@@ -80,6 +80,98 @@ def cpu_baseline(M, X0, bytes_per_iter: float, budget_s: float):
                       f"the same algorithmic bytes per iteration as the GPU line"}
 
 
+SERVING_POOL = [("grid3d", 32, 8.0), ("grid3d", 64, 8.0), ("grid3d", 96, 8.0),
+                ("grid3d", 128, 8.0), ("rmat", 16, 8.0), ("rmat", 18, 16.0), ("rmat", 20, 32.0)]
+
+
+def serving_bench(args):
+    """Poisson stream of iterated-SpMM jobs over a pool of graphs (3D grids
+    32^3..128^3, R-MAT 2^16..2^20 with degree 8..32), k in {16,32,64,128},
+    FP32/BF16, T in 5..50, X_0 drawn on the device from a per-request seed.
+    Capacity is measured closed-loop; latency is reported at 0.8x capacity."""
+    import torch
+
+    import paper_2402_19364_amd as arrow
+    import workloads as W
+    from paper_2402_19364_amd.serve import GpuEngine, Request, Server, latency_stats
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(5000)
+    decs, sizes = {}, {}
+    t0 = time.perf_counter()
+    for kind, size, deg in SERVING_POOL:
+        name = f"{kind}{size}" + (f"_d{int(deg)}" if kind == "rmat" else "")
+        vals = "sym_laplacian" if kind == "grid3d" else "row_normalized"
+        M = W.make_matrix(kind, size, vals, 5100 + size, 5200 + size, deg)
+        b = 1024 if M.n <= 300_000 else 2048
+        decs[name] = arrow.Decomposition.from_matrix(M, b, seed=5300 + size)
+        sizes[name] = (M.n, M.nnz)
+        del M
+    t_setup = time.perf_counter() - t0
+    log(f"[serving] pool of {len(decs)} graphs decomposed in {t_setup:.1f}s")
+    names = sorted(decs)
+
+    def make(count, seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for rid in range(count):
+            out.append(Request(rid, names[r.integers(len(names))], None, int(r.integers(5, 51)),
+                               "f32" if r.random() < 0.5 else "bf16", 0.0,
+                               width=int(r.choice([16, 32, 64, 128])), x0_seed=rid,
+                               keep_on_device=True))
+        return out
+
+    def work_bytes(req):
+        n, nnz = sizes[req.graph]
+        es = 4 if req.dtype == "f32" else 2
+        return req.iters * (nnz * 8 + 2 * n * req.k * es)
+
+    budget = int(args.serving_budget_gib * (1 << 30))
+    srv = Server(GpuEngine(0), budget)
+    for name, d in decs.items():
+        srv.register_graph(name, d)
+    # warm-up: one request per graph (plan upload, allocator)
+    srv.run([Request(900000 + i, g, None, 2, "f32", 0.0, width=16, x0_seed=i,
+                     keep_on_device=True) for i, g in enumerate(names)], bypass=True)
+    closed = make(args.serving_requests, 1)
+    t0 = time.perf_counter()
+    srv.run(closed, bypass=True)
+    makespan = time.perf_counter() - t0
+    mu = len(closed) / makespan
+    log(f"[serving] closed loop: {len(closed)} requests in {makespan:.2f}s -> {mu:.1f} req/s")
+    results = {}
+    for frac in args.serving_load:
+        reqs = make(args.serving_requests, 2 + int(frac * 100))
+        t = 0.0
+        for r in reqs:
+            t += rng.exponential(1.0 / (frac * mu))
+            r.arrival = t
+        t0 = time.perf_counter()
+        done = srv.run(reqs, bypass=True)
+        span = time.perf_counter() - t0
+        st = latency_stats(done)
+        results[f"{frac:g}"] = {
+            "offered_qps": round(frac * mu, 2), "achieved_qps": round(len(done) / span, 2),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "mean_ms": round(st["mean_ms"], 3),
+            "GBps": round(sum(work_bytes(r) for r in done) / span / 1e9, 1)}
+        log(f"[serving] load {frac:g}: {results[f'{frac:g}']}")
+    line = {
+        "metric": "serving latency of iterated arrow-SpMM jobs (continuous batching)",
+        "value": results[f"{args.serving_load[0]:g}"]["p99_ms"], "unit": "ms (p99)",
+        "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": "serving", "pool": {k: {"n": v[0], "nnz": v[1]}
+                                                    for k, v in sizes.items()},
+                   "requests": args.serving_requests, "k": [16, 32, 64, 128],
+                   "dtype": ["f32", "bf16"], "iters": "U{5..50}",
+                   "hbm_budget_GiB": args.serving_budget_gib},
+        "capacity_qps": round(mu, 2), "loads": results,
+        "peak_admitted_GiB": round(srv.peak_used / 2 ** 30, 2),
+        "widest_batch": srv.max_group_width, "setup_s": round(t_setup, 1),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +187,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run the streaming copy kernel N times over 1 GiB")
+    ap.add_argument("--serving", action="store_true", help="run the serving benchmark")
+    ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--serving-load", type=float, nargs="+", default=[0.8, 0.5, 0.95])
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -111,6 +207,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.serving:
+        serving_bench(args)
+        return
 
     if args.copy_calib:
         nbytes = 1 << 30

@@ -36,19 +36,22 @@ import numpy as np
 class Request:
     rid: int
     graph: str
-    x0: np.ndarray            # host FP32, n x k, original order
+    x0: Optional[np.ndarray]  # host FP32, n x k, original order (or None: use x0_seed)
     iters: int
     dtype: str = "f32"
     arrival: float = 0.0      # seconds on the server clock
+    width: int = 0            # k when x0 is None
+    x0_seed: int = 0          # X_0 ~ N(0, 1) drawn on the device from this seed
+    keep_on_device: bool = False  # leave the result as a device tensor
     # filled in by the server
     admitted: Optional[float] = None
     done: Optional[float] = None
-    result: Optional[np.ndarray] = None
+    result: Optional[object] = None     # X_T, original order (host array or device tensor)
     norms: Optional[np.ndarray] = None  # FP64 [iters, k]
 
     @property
     def k(self) -> int:
-        return int(self.x0.shape[1])
+        return int(self.x0.shape[1]) if self.x0 is not None else int(self.width)
 
     @property
     def latency(self) -> Optional[float]:
@@ -268,9 +271,16 @@ class GpuEngine:
         k = req.k
         scaled = req.dtype in ("f16", "f8e4m3")
         with torch.cuda.stream(stream):
+            if req.x0 is not None:
+                x0 = torch.from_numpy(np.ascontiguousarray(req.x0, dtype=np.float32)).to(
+                    self.dev, non_blocking=False)
+            else:
+                gen = torch.Generator(device=self.dev)
+                gen.manual_seed(int(req.x0_seed))
+                x0 = torch.randn((plan.n, k), generator=gen, dtype=torch.float32,
+                                 device=self.dev)
             st = {
-                "x0": torch.from_numpy(np.ascontiguousarray(req.x0, dtype=np.float32)).to(
-                    self.dev, non_blocking=False),
+                "x0": x0,
                 "buf": [plan.empty(k, req.dtype) for _ in range(2)],
                 "ws_bytes": plan.workspace_size(k, req.dtype),
                 "inv": [torch.zeros(k, dtype=torch.float64, device=self.dev) for _ in range(2)],
@@ -282,6 +292,7 @@ class GpuEngine:
             plan.permute_in(st["x0"], st["buf"][0], req.dtype,
                             x_scale=st["sc"][0] if scaled else None,
                             x_maxabs=st["mx"][0] if scaled else None, stream=stream)
+            del st["x0"]
         return st
 
     def step(self, plan, states, steps, stream):
@@ -331,7 +342,7 @@ class GpuEngine:
             plan.permute_out(last, out, st["dtype"],
                              x_scale=st["sc"][(t + 1) % 2] if st["scaled"] else None,
                              col_factor=st["inv"][t % 2], stream=stream)
-            req.result = out.cpu().numpy()
+            req.result = out if req.keep_on_device else out.cpu().numpy()
             req.norms = st["norms"].cpu().numpy()
         stream.synchronize()
         st.clear()
