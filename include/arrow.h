@@ -268,6 +268,21 @@ arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *
                               const float *val, const float *x, float *y, int64_t k, int64_t ld,
                               double *sumsq_ws, double *norms, void *stream);
 
+/*
+ * The vendor CSR SpMM (rocSPARSE generic API) as a second comparison
+ * baseline: y = A x with the same device CSR and row-major FP32 x / y
+ * (stride ld).  create does the buffer-size query, allocation and
+ * preprocessing (synchronous); run enqueues one product on the stream given
+ * at creation.  `alg` is a rocsparse_spmm_alg value (0 = library default).
+ */
+typedef struct arrow_rocsparse_s *arrow_rocsparse_t;
+arrow_status_t arrow_rocsparse_create(int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                      const int32_t *col, const float *val, const float *x,
+                                      float *y, int64_t k, int64_t ld, int32_t alg, void *stream,
+                                      arrow_rocsparse_t *out);
+arrow_status_t arrow_rocsparse_run(arrow_rocsparse_t ctx);
+void arrow_rocsparse_destroy(arrow_rocsparse_t ctx);
+
 /* Streaming copy of `bytes` (multiple of 16) from src to dst: HBM calibration. */
 arrow_status_t arrow_copy(const void *src, void *dst, int64_t bytes, void *stream);
 

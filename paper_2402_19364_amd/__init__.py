@@ -69,6 +69,8 @@ def _load():
         "arrow_copy": [P, P, I64, P],
         "arrow_profile_enable": [P, I32],
         "arrow_profile_query": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)],
+        "arrow_rocsparse_create": [I64, I64, P, P, P, P, P, I64, I64, I32, P, pp],
+        "arrow_rocsparse_run": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -78,6 +80,8 @@ def _load():
     lib.arrow_decomp_destroy.restype = None
     lib.arrow_plan_destroy.argtypes = [P]
     lib.arrow_plan_destroy.restype = None
+    lib.arrow_rocsparse_destroy.argtypes = [P]
+    lib.arrow_rocsparse_destroy.restype = None
     for name in ("arrow_status_string",):
         getattr(lib, name).argtypes = [I32]
         getattr(lib, name).restype = ctypes.c_char_p
@@ -380,6 +384,35 @@ def csr_spmm(n: int, row_ptr, col, val, x, y, sumsq_ws=None, norms=None, stream=
                                   x.shape[1], ld, _tptr(sumsq_ws), _tptr(norms),
                                   _stream_handle(stream)))
     return y
+
+
+class RocsparseSpmm:
+    """The vendor CSR SpMM as a comparison baseline (y = A x on one stream)."""
+
+    def __init__(self, n, row_ptr, col, val, x, y, alg: int = 0, stream=None):
+        ld = _rows(x, "x")
+        if tuple(y.shape) != tuple(x.shape) or _rows(y, "y") != ld:
+            raise ValueError("x and y must have the same shape and row stride")
+        h = ctypes.c_void_p()
+        _check(_load().arrow_rocsparse_create(n, col.numel(), _tptr(row_ptr), _tptr(col),
+                                              _tptr(val), _tptr(x), _tptr(y), x.shape[1], ld,
+                                              alg, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = (row_ptr, col, val, x, y)
+
+    def run(self):
+        _check(_load().arrow_rocsparse_run(self._h))
+
+    def close(self):
+        if self._h and self._h.value:
+            _load().arrow_rocsparse_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def copy(src, dst, nbytes: int, stream=None):
