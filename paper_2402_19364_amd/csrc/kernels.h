@@ -12,10 +12,6 @@ enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
 constexpr int kNumXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
 constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
-#ifndef ARROW_ROWS_PER_LANE
-#define ARROW_ROWS_PER_LANE 1
-#endif
-constexpr int kRowsPerLane = ARROW_ROWS_PER_LANE;  // rows a lane group gathers for at once
 
 // One row pass over a CSR-like set of rows.
 struct RowPass {
@@ -36,6 +32,7 @@ struct RowPass {
 struct Tile {
     const void *x;
     int64_t ldx;
+    int64_t x_span;       // bytes from x to the end of the last row's tile
     const float *s;       // partial-row buffer (FP32), read by the upper / level-0 passes
     float *s_out;         // partial-row buffer written by the chunk / upper passes
     int64_t lds;

@@ -93,14 +93,23 @@ __device__ __forceinline__ uint32_t f32_to_f8(float f) {  // RNE, saturating to 
     return code | sign;
 }
 
+// 16 bytes at base + off: a wave-uniform base (SGPRs) plus a 32-bit per-lane
+// byte offset, so a gather costs one VGPR of address and no 64-bit math.
+__device__ __forceinline__ vu4 load16(const char *base, uint32_t off) {
+    return *reinterpret_cast<const vu4 *>(base + off);
+}
+__device__ __forceinline__ vu4 load16(const char *base, uint64_t off) {
+    return *reinterpret_cast<const vu4 *>(base + off);
+}
+
 template <int DT> struct Fmt;
 template <> struct Fmt<kF32> {
     static constexpr int kVec = 4;
     static constexpr float kMax = 3.402823466e38f;
     static constexpr bool kScaled = false;
-    __device__ static void load(const void *p, float (&v)[kVec]) {
-        float4 a = *reinterpret_cast<const float4 *>(p);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    __device__ static void decode(vu4 a, float (&v)[kVec]) {
+        v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y);
+        v[2] = __uint_as_float(a.z); v[3] = __uint_as_float(a.w);
     }
     // Rounds v in place to the stored value and writes it.
     __device__ static void store(void *p, float (&v)[kVec]) {
@@ -112,8 +121,7 @@ template <> struct Fmt<kBF16> {
     static constexpr int kVec = 8;
     static constexpr float kMax = 3.38953139e38f;
     static constexpr bool kScaled = false;
-    __device__ static void load(const void *p, float (&v)[kVec]) {
-        uint4 a = *reinterpret_cast<const uint4 *>(p);
+    __device__ static void decode(vu4 a, float (&v)[kVec]) {
         uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -138,8 +146,7 @@ template <> struct Fmt<kF16> {
     static constexpr int kVec = 8;
     static constexpr float kMax = 65504.0f;
     static constexpr bool kScaled = true;
-    __device__ static void load(const void *p, float (&v)[kVec]) {
-        uint4 a = *reinterpret_cast<const uint4 *>(p);
+    __device__ static void decode(vu4 a, float (&v)[kVec]) {
         uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -164,8 +171,7 @@ template <> struct Fmt<kF8E4M3> {
     static constexpr int kVec = 16;
     static constexpr float kMax = 448.0f;
     static constexpr bool kScaled = true;
-    __device__ static void load(const void *p, float (&v)[kVec]) {
-        uint4 a = *reinterpret_cast<const uint4 *>(p);
+    __device__ static void decode(vu4 a, float (&v)[kVec]) {
         uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -219,15 +225,14 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 // entries of its row from LDS and issues their 8 independent X-row loads
 // before accumulating.  Entries beyond the staged range (a block with more
 // entries than fit) are read from global memory.
-template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL>
+template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32>
 __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) {
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;             // lanes per row
     constexpr int RPW = kWave / LPR;          // rows per wave and round
     constexpr int RPR = RPW * kWaves;         // rows per workgroup and round
-    constexpr int UNR = 32 / VEC > 1 ? 32 / VEC : 2;  // entries gathered per row and batch
-    constexpr int P = kRowsPerLane;                    // rows per lane group and round
+    constexpr int UNR = 8;                    // entries gathered per row and batch
     static_assert(LPR >= 1 && kWave % LPR == 0, "tile width");
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     using IdxT = typename std::conditional<CODE16, uint16_t, int32_t>::type;
@@ -245,8 +250,11 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     const int sub = lane % LPR;
     const IdxT *gidx = reinterpret_cast<const IdxT *>(rp.idx);
 
-    const char *xb = reinterpret_cast<const char *>(t.x) + (int64_t)sub * 16;
-    const int64_t xstride = t.ldx * kElem;
+    // X byte offsets fit 32 bits when the matrix spans less than 4 GiB
+    using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
+    const char *xbase = reinterpret_cast<const char *>(t.x);
+    const Off xstride = (Off)(t.ldx * kElem);
+    const Off xlane = (Off)(sub * 16);
 
     // per-column factors of the final pass (this lane's VEC columns)
     float fac[VEC], cinv[VEC], cscale[VEC];
@@ -293,85 +301,68 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
         __syncthreads();
         const int e0 = s_ptr[0];
         const int ne = s_ptr[nr] - e0;
-        const int ns = ne < kStageEntries ? ne : kStageEntries;
-        for (int i = tid; i < ns; i += kBlockThreads) {
-            s_idx[i] = gidx[e0 + i];
-            s_val[i] = rp.val[e0 + i];
+        // Block-uniform choice: the block's entries come from LDS when they fit,
+        // otherwise every entry is read from global memory.
+        const bool staged = ne <= kStageEntries;
+        if (staged) {
+            for (int i = tid; i < ne; i += kBlockThreads) {
+                s_idx[i] = gidx[e0 + i];
+                s_val[i] = rp.val[e0 + i];
+            }
         }
         __syncthreads();
 
-        // P rows per lane group and round: their gathers are issued together
-        for (int rl0 = wave * RPW + g; rl0 < nr; rl0 += RPR * P) {
-            float acc[P][VEC];
-            int a[P], len[P];
-            int maxlen = 0;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int rl = rl0 + p * RPR;
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[p][i] = 0.0f;
-                a[p] = 0;
-                len[p] = 0;
-                if (rl < nr) {
-                    a[p] = s_ptr[rl] - e0;
-                    len[p] = s_ptr[rl + 1] - e0 - a[p];
-                }
-                maxlen = len[p] > maxlen ? len[p] : maxlen;
-            }
-            for (int e = 0; e < maxlen; e += UNR) {
-                float av[P][UNR];
-                int cv[P][UNR];  // X row numbers (the byte offset is formed at the load)
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const int rb = (int)(row0 + rl0 + p * RPR) - rp.b;  // band start (codes)
-#pragma unroll
-                    for (int u = 0; u < UNR; ++u) {
-                        av[p][u] = 0.0f;
-                        cv[p][u] = 0;
-                        if (e + u < len[p]) {
-                            const int ee = a[p] + e + u;
-                            IdxT code;
-                            if (ee < ns) {
-                                code = s_idx[ee];
-                                av[p][u] = s_val[ee];
-                            } else {
-                                code = gidx[e0 + ee];
-                                av[p][u] = rp.val[e0 + ee];
-                            }
-                            if constexpr (CODE16) {
-                                const int c = code;
-                                cv[p][u] = c <= 2 * rp.b ? rb + c : c - 2 * rp.b - 1;
-                            } else {
-                                cv[p][u] = code;
-                            }
-                        }
-                    }
-                }
-                float xv[P][UNR][VEC];
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-#pragma unroll
-                    for (int u = 0; u < UNR; ++u) {
-                        if (e + u < len[p]) {
-                            F::load(xb + (int64_t)cv[p][u] * xstride, xv[p][u]);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < VEC; ++i) xv[p][u][i] = 0.0f;
-                        }
-                    }
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-#pragma unroll
-                    for (int u = 0; u < UNR; ++u)
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i)
-                            acc[p][i] = fmaf(av[p][u], xv[p][u][i], acc[p][i]);
-            }
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int rl = rl0 + p * RPR;
-                if (rl >= nr) continue;
+        auto rows = [&](auto staged_tag) {
+            constexpr bool STAGED = decltype(staged_tag)::value;
+            for (int rl = wave * RPW + g; rl < nr; rl += RPR) {
                 const int64_t r = row0 + rl;
+                const int a = s_ptr[rl] - e0;
+                const int len = s_ptr[rl + 1] - e0 - a;
+                const int rb = (int)r - rp.b;  // band start (16-bit codes)
+                float acc[VEC];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+                for (int e = 0; e < len; e += UNR) {
+                    // padding slots of the last batch re-read the batch's first
+                    // entry (a valid address) and contribute an exact zero
+                    float av[UNR];
+                    Off off[UNR];
+                    bool ok[UNR];
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        ok[u] = e + u < len;
+                        const int ee = a + (ok[u] ? e + u : e);
+                        IdxT code;
+                        float v;
+                        if constexpr (STAGED) {
+                            code = s_idx[ee];
+                            v = s_val[ee];
+                        } else {
+                            code = gidx[e0 + ee];
+                            v = rp.val[e0 + ee];
+                        }
+                        av[u] = ok[u] ? v : 0.0f;
+                        int c;
+                        if constexpr (CODE16) {
+                            const int cc = code;
+                            c = cc <= 2 * rp.b ? rb + cc : cc - 2 * rp.b - 1;
+                        } else {
+                            c = code;
+                        }
+                        off[u] = (Off)c * xstride + xlane;
+                    }
+                    vu4 xr[UNR];
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) xr[u] = load16(xbase, off[u]);
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        const vu4 w = ok[u] ? xr[u] : vu4{0u, 0u, 0u, 0u};
+                        float xv[VEC];
+                        F::decode(w, xv);
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) acc[i] = fmaf(av[u], xv[i], acc[i]);
+                    }
+                }
                 if constexpr (CONTRIB) {
                     const int c0 = s_cptr[rl], c1 = s_cptr[rl + 1];
                     for (int c = c0; c < c1; ++c) {
@@ -379,34 +370,38 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
 #pragma unroll
                         for (int i = 0; i < VEC; i += 4) {
                             float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
-                            acc[p][i] += s4.x;
-                            acc[p][i + 1] += s4.y;
-                            acc[p][i + 2] += s4.z;
-                            acc[p][i + 3] += s4.w;
+                            acc[i] += s4.x;
+                            acc[i + 1] += s4.y;
+                            acc[i + 2] += s4.z;
+                            acc[i + 3] += s4.w;
                         }
                     }
                 }
                 if constexpr (FINAL) {
 #pragma unroll
-                    for (int i = 0; i < VEC; ++i) acc[p][i] = acc[p][i] * fac[i] * cinv[i];
+                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * fac[i] * cinv[i];
                     char *yp =
                         reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
-                    F::store(yp, acc[p]);  // acc now holds the stored (rounded) codes as floats
+                    F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) {
-                        const double v = (double)acc[p][i] * (double)cscale[i];
+                        const double v = (double)acc[i] * (double)cscale[i];
                         ssq[i] += v * v;
-                        cmax[i] = fmaxf(cmax[i], fabsf(acc[p][i]));
+                        if constexpr (F::kScaled) cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
                     }
                 } else {
                     float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
 #pragma unroll
                     for (int i = 0; i < VEC; i += 4)
                         *reinterpret_cast<float4 *>(sp + i) =
-                            make_float4(acc[p][i], acc[p][i + 1], acc[p][i + 2], acc[p][i + 3]);
+                            make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
                 }
             }
-        }
+        };
+        if (staged)
+            rows(std::true_type{});
+        else
+            rows(std::false_type{});
     }
 
     if constexpr (FINAL) {
@@ -567,7 +562,8 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
     const int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
     if (p >= n) return;
     float v[VEC];
-    F::load(reinterpret_cast<const char *>(yp) + p * ld * kElem + sub * 16, v);
+    F::decode(*reinterpret_cast<const vu4 *>(reinterpret_cast<const char *>(yp) + p * ld * kElem +
+                                              sub * 16), v);
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
         const int j = sub * VEC + i;
@@ -607,31 +603,38 @@ __global__ __launch_bounds__(kBlockThreads) void copy_kernel(const vu4 *src, vu4
 
 namespace {
 
-template <int KT, int DT>
-hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const Tile &t,
+template <int KT, int DT, bool OFF32>
+hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
                         hipStream_t s) {
     dim3 grid(rp.nwg), block(dev::kBlockThreads);
     if (rp.nwg <= 0) return hipSuccess;
     switch (mode) {
     case kPassChunk:
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, false>), grid, block, 0, s, rp, t);
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, false, OFF32>), grid, block, 0, s, rp, t);
         break;
     case kPassUpper:
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false>), grid, block, 0, s, rp, t);
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false, OFF32>), grid, block, 0, s, rp, t);
         break;
     case kPassLevel0:
         if (code16)
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true>), grid, block, 0, s, rp, t);
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32>), grid, block, 0, s, rp, t);
         else
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, true>), grid, block, 0, s, rp, t);
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, true, OFF32>), grid, block, 0, s, rp, t);
         break;
     case kPassPlain:  // plain CSR: int32 columns, no contributions, final store
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, true>), grid, block, 0, s, rp, t);
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, true, OFF32>), grid, block, 0, s, rp, t);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KT, int DT>
+hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const Tile &t, hipStream_t s) {
+    if (t.x_span < (int64_t(1) << 32))
+        return launch_row_o<KT, DT, true>(mode, code16, rp, t, s);
+    return launch_row_o<KT, DT, false>(mode, code16, rp, t, s);
 }
 
 template <int DT>

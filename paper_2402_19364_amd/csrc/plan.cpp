@@ -377,6 +377,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
         Tile t{};
         t.x = static_cast<const char *>(op.x) + c0 * es;
         t.ldx = op.ldx;
+        t.x_span = ((n - 1) * op.ldx + kt) * es;
         t.s = sbuf + c0;
         t.s_out = sbuf + c0;
         t.lds = k;
@@ -464,6 +465,7 @@ arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, 
         Tile t{};
         t.x = x + c0;
         t.ldx = ld;
+        t.x_span = ((n - 1) * ld + kt) * 4;
         t.y = y + c0;
         t.ldy = ld;
         t.part_sumsq = ws ? ws + c0 * nb : nullptr;
