@@ -12,6 +12,8 @@ enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
 constexpr int kNumXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
 constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
+constexpr int kStageLists = 1024;    // listed partial rows staged in LDS per block
+constexpr int kChunk = 64;           // entries per chunk of a head row or long row
 
 // One row pass over a CSR-like set of rows.
 struct RowPass {
@@ -57,7 +59,6 @@ struct NormArgs {
     float *maxabs;
 };
 
-int rows_per_round(int kt, int dtype);
 hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
                            const Tile &t, hipStream_t s);
 hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s);

@@ -40,12 +40,16 @@ constexpr int kWaves = kBlockThreads / kWave;
 // Native clang vectors (the non-temporal builtins need them).
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef unsigned vu4 __attribute__((ext_vector_type(4)));
+typedef unsigned vu2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void store_nt(void *p, vf4 v) {
     __builtin_nontemporal_store(v, reinterpret_cast<vf4 *>(p));
 }
 __device__ __forceinline__ void store_nt(void *p, vu4 v) {
     __builtin_nontemporal_store(v, reinterpret_cast<vu4 *>(p));
+}
+__device__ __forceinline__ void store_nt(void *p, vu2 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<vu2 *>(p));
 }
 
 // ---------------------------------------------------------------------------
@@ -93,18 +97,22 @@ __device__ __forceinline__ uint32_t f32_to_f8(float f) {  // RNE, saturating to 
     return code | sign;
 }
 
-// 16 bytes at base + off: a wave-uniform base (SGPRs) plus a 32-bit per-lane
-// byte offset, so a gather costs one VGPR of address and no 64-bit math.
-__device__ __forceinline__ vu4 load16(const char *base, uint32_t off) {
-    return *reinterpret_cast<const vu4 *>(base + off);
+// One lane word at base + off: a wave-uniform base (SGPRs) plus a 32-bit
+// per-lane byte offset, so a gather costs one VGPR of address and no 64-bit math.
+template <class W, class O>
+__device__ __forceinline__ W loadw(const char *base, O off) {
+    return *reinterpret_cast<const W *>(base + off);
 }
-__device__ __forceinline__ vu4 load16(const char *base, uint64_t off) {
-    return *reinterpret_cast<const vu4 *>(base + off);
+template <class O>
+__device__ __forceinline__ vu4 load16(const char *base, O off) {
+    return loadw<vu4>(base, off);
 }
 
 template <int DT> struct Fmt;
 template <> struct Fmt<kF32> {
+    using Raw = vu4;  // one lane's 16 bytes
     static constexpr int kVec = 4;
+    static constexpr int kBytes = 16;
     static constexpr float kMax = 3.402823466e38f;
     static constexpr bool kScaled = false;
     __device__ static void decode(vu4 a, float (&v)[kVec]) {
@@ -118,7 +126,9 @@ template <> struct Fmt<kF32> {
     }
 };
 template <> struct Fmt<kBF16> {
+    using Raw = vu4;
     static constexpr int kVec = 8;
+    static constexpr int kBytes = 16;
     static constexpr float kMax = 3.38953139e38f;
     static constexpr bool kScaled = false;
     __device__ static void decode(vu4 a, float (&v)[kVec]) {
@@ -143,7 +153,9 @@ template <> struct Fmt<kBF16> {
     }
 };
 template <> struct Fmt<kF16> {
+    using Raw = vu4;
     static constexpr int kVec = 8;
+    static constexpr int kBytes = 16;
     static constexpr float kMax = 65504.0f;
     static constexpr bool kScaled = true;
     __device__ static void decode(vu4 a, float (&v)[kVec]) {
@@ -168,20 +180,22 @@ template <> struct Fmt<kF16> {
     }
 };
 template <> struct Fmt<kF8E4M3> {
-    static constexpr int kVec = 16;
+    using Raw = vu2;  // 8 values per lane keep the per-column state small
+    static constexpr int kVec = 8;
+    static constexpr int kBytes = 8;
     static constexpr float kMax = 448.0f;
     static constexpr bool kScaled = true;
-    __device__ static void decode(vu4 a, float (&v)[kVec]) {
-        uint32_t w[4] = {a.x, a.y, a.z, a.w};
+    __device__ static void decode(vu2 a, float (&v)[kVec]) {
+        uint32_t w[2] = {a.x, a.y};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) v[4 * i + j] = f8_to_f32((w[i] >> (8 * j)) & 0xFFu);
     }
     __device__ static void store(void *p, float (&v)[kVec]) {
-        uint32_t w[4];
+        uint32_t w[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 2; ++i) {
             uint32_t acc = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -191,7 +205,7 @@ template <> struct Fmt<kF8E4M3> {
             }
             w[i] = acc;
         }
-        vu4 a = {w[0], w[1], w[2], w[3]};
+        vu2 a = {w[0], w[1]};
         store_nt(p, a);
     }
 };
@@ -239,6 +253,7 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
 
     __shared__ int32_t s_ptr[kMaxBlockRows + 1];
     __shared__ int32_t s_cptr[CONTRIB ? kMaxBlockRows + 1 : 1];
+    __shared__ int32_t s_cidx[CONTRIB ? kStageLists : 1];
     __shared__ IdxT s_idx[kStageEntries];
     __shared__ float s_val[kStageEntries];
 
@@ -254,37 +269,38 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
     const char *xbase = reinterpret_cast<const char *>(t.x);
     const Off xstride = (Off)(t.ldx * kElem);
-    const Off xlane = (Off)(sub * 16);
+    const Off xlane = (Off)(sub * F::kBytes);
 
     // per-column factors of the final pass (this lane's VEC columns)
-    float fac[VEC], cinv[VEC], cscale[VEC];
+    // Output scale of column j for the scaled formats: the power of two c_j with
+    // |Y[:, j]| <= ||A||_inf * x_scale_j * max|code_j| * (1/nu_j) <= c_j * max.
+    auto out_scale = [&](int j) -> float {
+        const float xs = t.x_scale ? t.x_scale[j] : 1.0f;
+        const double inv = t.x_inv_norm ? t.x_inv_norm[j] : 1.0;
+        const float xm = t.x_maxabs ? t.x_maxabs[j] : F::kMax;
+        return pow2_ceil((double)t.a_inf * (double)xs * (double)xm * inv / (double)F::kMax);
+    };
+    // mul = x_scale * (1/nu) / c (c exact power of two); sums of squares are
+    // kept in code units and scaled by c^2 once at the end (exact)
+    float mul[VEC];
     double ssq[VEC];
-    float cmax[VEC];
+    float cmax[F::kScaled ? VEC : 1];
     if constexpr (FINAL) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const int j = sub * VEC + i;
             const float xs = t.x_scale ? t.x_scale[j] : 1.0f;
             const double inv = t.x_inv_norm ? t.x_inv_norm[j] : 1.0;
-            fac[i] = (float)((double)xs * inv);
+            const float fac = (float)((double)xs * inv);
             if constexpr (F::kScaled) {
-                const float xm = t.x_maxabs ? t.x_maxabs[j] : F::kMax;
-                const float c = pow2_ceil((double)t.a_inf * (double)xs * (double)xm * inv /
-                                          (double)F::kMax);
-                cscale[i] = c;
-                cinv[i] = 1.0f / c;  // exact: c is a power of two
+                const float c = out_scale(j);
+                mul[i] = fac * (1.0f / c);
+                cmax[i] = 0.0f;
+                if (wg == 0 && wave == 0 && g == 0 && t.y_scale) t.y_scale[j] = c;
             } else {
-                cscale[i] = 1.0f;
-                cinv[i] = 1.0f;
+                mul[i] = fac;
             }
             ssq[i] = 0.0;
-            cmax[i] = 0.0f;
-        }
-        if constexpr (F::kScaled) {
-            if (wg == 0 && wave == 0 && g == 0 && t.y_scale) {
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) t.y_scale[sub * VEC + i] = cscale[i];
-            }
         }
     }
 
@@ -309,6 +325,16 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                 s_idx[i] = gidx[e0 + i];
                 s_val[i] = rp.val[e0 + i];
             }
+        }
+        // the block's list of partial rows, staged the same way
+        int cb = 0;
+        bool cstaged = true;
+        if constexpr (CONTRIB) {
+            cb = s_cptr[0];
+            const int nc = s_cptr[nr] - cb;
+            cstaged = nc <= kStageLists;
+            if (cstaged)
+                for (int i = tid; i < nc; i += kBlockThreads) s_cidx[i] = rp.cidx[cb + i];
         }
         __syncthreads();
 
@@ -351,12 +377,12 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                         }
                         off[u] = (Off)c * xstride + xlane;
                     }
-                    vu4 xr[UNR];
+                    typename F::Raw xr[UNR];
 #pragma unroll
-                    for (int u = 0; u < UNR; ++u) xr[u] = load16(xbase, off[u]);
+                    for (int u = 0; u < UNR; ++u) xr[u] = loadw<typename F::Raw>(xbase, off[u]);
 #pragma unroll
                     for (int u = 0; u < UNR; ++u) {
-                        const vu4 w = ok[u] ? xr[u] : vu4{0u, 0u, 0u, 0u};
+                        const typename F::Raw w = ok[u] ? xr[u] : typename F::Raw{};
                         float xv[VEC];
                         F::decode(w, xv);
 #pragma unroll
@@ -364,28 +390,52 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                     }
                 }
                 if constexpr (CONTRIB) {
-                    const int c0 = s_cptr[rl], c1 = s_cptr[rl + 1];
-                    for (int c = c0; c < c1; ++c) {
-                        const float *srow = t.s + (int64_t)rp.cidx[c] * t.lds + sub * VEC;
+                    // listed partial rows (FP32), gathered in batches like the
+                    // entries: 8 wide while more than 2 remain, then 2 wide
+                    const int c0 = s_cptr[rl] - cb, c1 = s_cptr[rl + 1] - cb;
+                    const char *sbase = reinterpret_cast<const char *>(t.s);
+                    auto batch = [&](int c, auto width_tag) {
+                        constexpr int W = decltype(width_tag)::value;
+                        uint64_t soff[W];
+                        bool ok[W];
 #pragma unroll
-                        for (int i = 0; i < VEC; i += 4) {
-                            float4 s4 = *reinterpret_cast<const float4 *>(srow + i);
-                            acc[i] += s4.x;
-                            acc[i + 1] += s4.y;
-                            acc[i + 2] += s4.z;
-                            acc[i + 3] += s4.w;
+                        for (int u = 0; u < W; ++u) {
+                            ok[u] = c + u < c1;
+                            const int cc = ok[u] ? c + u : c;
+                            const int row = cstaged ? s_cidx[cc] : rp.cidx[cb + cc];
+                            soff[u] = ((uint64_t)row * (uint64_t)t.lds + (uint64_t)(sub * VEC)) * 4;
                         }
-                    }
+                        vu4 sv[W][VEC / 4];
+#pragma unroll
+                        for (int u = 0; u < W; ++u)
+#pragma unroll
+                            for (int q = 0; q < VEC / 4; ++q)
+                                sv[u][q] = load16(sbase, soff[u] + (uint64_t)(16 * q));
+#pragma unroll
+                        for (int u = 0; u < W; ++u)
+#pragma unroll
+                            for (int q = 0; q < VEC / 4; ++q) {
+                                const vu4 w = ok[u] ? sv[u][q] : vu4{0u, 0u, 0u, 0u};
+                                acc[4 * q] += __uint_as_float(w.x);
+                                acc[4 * q + 1] += __uint_as_float(w.y);
+                                acc[4 * q + 2] += __uint_as_float(w.z);
+                                acc[4 * q + 3] += __uint_as_float(w.w);
+                            }
+                    };
+                    constexpr int WIDE = VEC >= 16 ? 2 : (VEC >= 8 ? 4 : 8);
+                    int c = c0;
+                    for (; c1 - c > 2; c += WIDE) batch(c, std::integral_constant<int, WIDE>{});
+                    if (c < c1) batch(c, std::integral_constant<int, 2>{});
                 }
                 if constexpr (FINAL) {
 #pragma unroll
-                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * fac[i] * cinv[i];
+                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * mul[i];
                     char *yp =
-                        reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * 16;
+                        reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * F::kBytes;
                     F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) {
-                        const double v = (double)acc[i] * (double)cscale[i];
+                        const double v = (double)acc[i];
                         ssq[i] += v * v;
                         if constexpr (F::kScaled) cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
                     }
@@ -412,7 +462,12 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             double v = ssq[i];
-            float m = cmax[i];
+            float m = 0.0f;
+            if constexpr (F::kScaled) {
+                const double c = out_scale(sub * VEC + i);
+                v *= c * c;  // exact: c is a power of two
+                m = cmax[i];
+            }
 #pragma unroll
             for (int off = LPR; off < kWave; off <<= 1) {
                 v += __shfl_xor(v, off);
@@ -434,6 +489,76 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
             }
             if (t.part_sumsq) t.part_sumsq[(int64_t)j * t.part_ld + wg] = v;
             if (t.part_max) t.part_max[(int64_t)j * t.part_ld + wg] = m;
+        }
+    }
+}
+
+// Chunk pass: each wave reduces one chunk (at most kChunk entries of a head
+// row or long row).  Its lane groups take interleaved entries, so all the
+// chunk's X-row gathers are in flight together; the group sums are combined
+// by a fixed butterfly over the group bits and group 0 writes the FP32
+// partial row.  A workgroup handles rows_per_block consecutive chunks.
+template <int KT, int DT, bool OFF32>
+__global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, Tile t) {
+    using F = Fmt<DT>;
+    constexpr int VEC = F::kVec;
+    constexpr int LPR = KT / VEC;
+    constexpr int RPW = kWave / LPR;                 // lane groups per wave
+    constexpr int PER = (kChunk + RPW - 1) / RPW;    // entries per group and chunk
+    constexpr int UNR = PER < 8 ? PER : 8;
+    constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
+    using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
+    const int wg = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int g = lane / LPR;
+    const int sub = lane % LPR;
+    const int32_t *gidx = reinterpret_cast<const int32_t *>(rp.idx);
+    const char *xbase = reinterpret_cast<const char *>(t.x);
+    const Off xstride = (Off)(t.ldx * kElem);
+    const Off xlane = (Off)(sub * F::kBytes);
+    const int64_t c_begin = (int64_t)wg * rp.rows_per_block;
+    const int64_t c_end =
+        c_begin + rp.rows_per_block < rp.nrows ? c_begin + rp.rows_per_block : rp.nrows;
+    for (int64_t ci = c_begin + wave; ci < c_end; ci += kWaves) {
+        const int e0 = rp.ptr[ci], e1 = rp.ptr[ci + 1];
+        float acc[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+        for (int e = e0 + g; e < e1; e += RPW * UNR) {
+            float av[UNR];
+            Off off[UNR];
+            bool ok[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int ee = e + u * RPW;
+                ok[u] = ee < e1;
+                const int es = ok[u] ? ee : e;
+                av[u] = ok[u] ? rp.val[es] : 0.0f;
+                off[u] = (Off)gidx[es] * xstride + xlane;
+            }
+            typename F::Raw xr[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) xr[u] = loadw<typename F::Raw>(xbase, off[u]);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const typename F::Raw w = ok[u] ? xr[u] : typename F::Raw{};
+                float xv[VEC];
+                F::decode(w, xv);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[i] = fmaf(av[u], xv[i], acc[i]);
+            }
+        }
+#pragma unroll
+        for (int off = LPR; off < kWave; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] += __shfl_xor(acc[i], off);
+        if (g == 0) {
+            float *sp = t.s_out + (int64_t)(rp.out_row0 + ci) * t.lds + sub * VEC;
+#pragma unroll
+            for (int i = 0; i < VEC; i += 4)
+                *reinterpret_cast<float4 *>(sp + i) =
+                    make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
         }
     }
 }
@@ -533,7 +658,7 @@ __global__ __launch_bounds__(kBlockThreads) void permute_in_kernel(
 #pragma unroll
             for (int i = 0; i < VEC; ++i) v[i] = v[i] / scale[sub * VEC + i];
         }
-        F::store(reinterpret_cast<char *>(xp) + (p * ld * kElem) + sub * 16, v);
+        F::store(reinterpret_cast<char *>(xp) + (p * ld * kElem) + sub * F::kBytes, v);
 #pragma unroll
         for (int i = 0; i < VEC; ++i) m[i] = fabsf(v[i]);
     }
@@ -562,8 +687,9 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
     const int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
     if (p >= n) return;
     float v[VEC];
-    F::decode(*reinterpret_cast<const vu4 *>(reinterpret_cast<const char *>(yp) + p * ld * kElem +
-                                              sub * 16), v);
+    F::decode(*reinterpret_cast<const typename F::Raw *>(reinterpret_cast<const char *>(yp) +
+                                                          p * ld * kElem + sub * F::kBytes),
+              v);
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
         const int j = sub * VEC + i;
@@ -610,7 +736,7 @@ hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
     if (rp.nwg <= 0) return hipSuccess;
     switch (mode) {
     case kPassChunk:
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, false, OFF32>), grid, block, 0, s, rp, t);
+        hipLaunchKernelGGL((dev::chunk_kernel<KT, DT, OFF32>), grid, block, 0, s, rp, t);
         break;
     case kPassUpper:
         hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false, OFF32>), grid, block, 0, s, rp, t);
@@ -676,11 +802,6 @@ hipError_t launch_perm_out_t(const void *yp, int64_t ld, const int32_t *vop, int
 
 }  // namespace
 
-int rows_per_round(int kt, int dtype) {
-    const int vec = dtype == kF32 ? 4 : (dtype == kF8E4M3 ? 16 : 8);
-    const int lpr = kt / vec;
-    return (dev::kWave / lpr) * dev::kWaves;
-}
 
 hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
                            const Tile &t, hipStream_t s) {

@@ -12,10 +12,9 @@
 namespace arrow {
 
 constexpr int kLongRow = 128;     // rows with more entries go through the chunk pass
-constexpr int kChunk = 64;        // entries per chunk
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
 constexpr int kBlocksPerWg = 4;                    // blocks walked by one workgroup
-constexpr int kChunksPerBlock = kStageEntries / kChunk;
+constexpr int kChunksPerBlock = 16;               // chunks per workgroup (4 per wave)
 
 struct ProfRec {
     int kernel;
