@@ -288,21 +288,28 @@ def main():
         step()
     torch.cuda.synchronize()
 
+    # timed region: K steps, events only at iteration boundaries
     it_events = [[torch.cuda.Event(enable_timing=True) for _ in range(T + 1)]
                  for _ in range(args.steps)]
     e_start = torch.cuda.Event(enable_timing=True)
     e_stop = torch.cuda.Event(enable_timing=True)
-    plan.profile(True)
     torch.cuda.synchronize()
     e_start.record()
     for s in range(args.steps):
         step(it_events[s])
     e_stop.record()
     torch.cuda.synchronize()
-    plan.profile(False)
     total_ms = e_start.elapsed_time(e_stop)
     ms_step = total_ms / args.steps
     iter_ms = np.array([ev[t].elapsed_time(ev[t + 1]) for ev in it_events for t in range(T)])
+    # the same K steps again with HIP events around every launch (on the launch
+    # stream) for the per-kernel durations of the roofline
+    plan.profile(True)
+    torch.cuda.synchronize()
+    for s in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(False)
 
     kb = {kid: plan.kernel_bytes(kid, k, dtype) for kid in arrow.KERNEL_NAMES}
     bytes_iter = sum(kb[kid] for kid in (arrow.KERNEL_CHUNKS, arrow.KERNEL_UPPER,

@@ -14,7 +14,7 @@ namespace arrow {
 constexpr int kLongRow = 128;     // rows with more entries go through the chunk pass
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
 constexpr int kBlocksPerWg = 4;                    // blocks walked by one workgroup
-constexpr int kChunksPerBlock = 16;               // chunks per workgroup (4 per wave)
+constexpr int kChunksPerBlock = 4;                // chunks per workgroup (one per wave)
 
 struct ProfRec {
     int kernel;
