@@ -11,7 +11,7 @@
 
 namespace arrow {
 
-constexpr int kLongRow = 128;     // rows with more entries go through the chunk pass
+constexpr int kLongRow = 32;      // rows with more entries go through the chunk pass
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
 constexpr int kBlocksPerWg = 4;                    // blocks walked by one workgroup
 constexpr int kChunksPerBlock = 4;                // chunks per workgroup (one per wave)
