@@ -363,9 +363,12 @@ def main():
         cn = torch.empty(k, dtype=torch.float64, device=dev)
         bufs2 = (cx, cy)
 
+        csr_batch = arrow.csr_batch(M.row_ptr)  # same gather-batch rule as the plan's passes
+
         def own(i, norm=True, r=(rp, col, val)):
             arrow.csr_spmm(M.n, r[0], r[1], r[2], bufs2[i % 2], bufs2[(i + 1) % 2],
-                           cws.view(torch.float64) if norm else None, cn if norm else None)
+                           cws.view(torch.float64) if norm else None, cn if norm else None,
+                           batch=csr_batch)
 
         c_full = time_iters(lambda i: own(i, True), 2 * T)
         c_spmm = time_iters(lambda i: own(i, False), 2 * T)
@@ -393,6 +396,7 @@ def main():
         own_spmm = float(np.median(c_spmm))
         best_spmm = min(own_spmm, best_vendor) if best_vendor is not None else own_spmm
         csr = {"kernel": "hand-written HIP CSR (as-generated order, int32 indices)",
+               "gather_batch": csr_batch,
                "iter_ms_p50": round(float(np.median(c_full)), 4),
                "iter_ms_p99": round(float(np.percentile(c_full, 99)), 4),
                "spmm_ms_p50": round(own_spmm, 4),
@@ -424,7 +428,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": w.describe(), "n": M.n,
                    "nnz": M.nnz, "k": k, "b": w.b, "iterations": T,
-                   "linear_arrangement": args.la, "levels": pinfo["levels"]},
+                   "linear_arrangement": args.la, "levels": pinfo["levels"],
+                   "gather_batch": {"upper": pinfo["upper_batch"],
+                                    "level0": pinfo["level0_batch"]}},
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "iter_ms_p50": round(p50, 4),
         "iter_ms_p99": round(float(np.percentile(iter_ms, 99)), 4),

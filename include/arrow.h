@@ -152,9 +152,26 @@ typedef struct {
     int64_t upper_rows;       /* rows of levels >= 1 that hold entries */
     int64_t contributions;    /* summands gathered by the level-0 pass */
     double a_inf_norm;        /* max_i sum_j |A_ij| (bounds the FP8/FP16 scales) */
+    int32_t upper_batch;      /* gather batch of the upper / level-0 passes: 0 = wide, */
+    int32_t level0_batch;     /* else entries gathered per row and batch (4..8) */
 } arrow_plan_info_t;
 
 arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);
+
+/*
+ * Gather batch of a row pass (kernel = ARROW_KERNEL_UPPER or
+ * ARROW_KERNEL_LEVEL0).  The rows of a pass are gathered in batches; a wide
+ * batch (0) takes 8 entries of a row and up to 8 listed partial rows at a
+ * time, a short batch u in [4, 8] takes u entries and 2 partial rows at a time
+ * with fewer registers, so more waves share a SIMD.  arrow_plan_create picks
+ * the smallest short batch that holds the entries of at least 99% of the
+ * pass's rows when at least 99% of them list at most 2 partial rows, and the
+ * wide batch otherwise; batch = -1 restores that choice.  Every batch
+ * computes the same sums in the same order (results agree up to the sign of
+ * a zero); operands whose X spans 4 GiB or more always take the wide batch.
+ * Not thread-safe against concurrent products on the same plan.
+ */
+arrow_status_t arrow_plan_set_batch(arrow_plan_t p, int32_t kernel, int32_t batch);
 
 /* Kernel ids for arrow_plan_kernel_bytes and the profiling counters. */
 enum {
@@ -264,9 +281,14 @@ arrow_status_t arrow_spmm_iterate(arrow_plan_t p, const void *x, void *y, int64_
  * arrow_csr_workspace_size bytes) and norms (device double[k]) are non-NULL.
  */
 arrow_status_t arrow_csr_workspace_size(int64_t n, int64_t k, size_t *bytes);
+/* Gather batch for arrow_csr_spmm from the host row_ptr int64[n+1], by the
+ * rule arrow_plan_create applies to its passes (0 = wide, else 4..8). */
+arrow_status_t arrow_csr_batch(int64_t n, const int64_t *row_ptr, int32_t *batch);
+/* batch: 0 (wide) or 4..8 entries gathered per row and batch (a schedule
+ * choice: every batch gives the same result). */
 arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *col,
                               const float *val, const float *x, float *y, int64_t k, int64_t ld,
-                              double *sumsq_ws, double *norms, void *stream);
+                              int32_t batch, double *sumsq_ws, double *norms, void *stream);
 
 /*
  * The vendor CSR SpMM (rocSPARSE generic API) as a second comparison

@@ -65,7 +65,9 @@ def _load():
         "arrow_spmm": [P, P, I32, P, SZ, P],
         "arrow_spmm_iterate": [P, P, P, I64, I64, I32, P, P, I32, U32, P, P, SZ, P],
         "arrow_csr_workspace_size": [I64, I64, ctypes.POINTER(SZ)],
-        "arrow_csr_spmm": [I64, P, P, P, P, P, I64, I64, P, P, P],
+        "arrow_csr_batch": [I64, P, ctypes.POINTER(I32)],
+        "arrow_csr_spmm": [I64, P, P, P, P, P, I64, I64, I32, P, P, P],
+        "arrow_plan_set_batch": [P, I32, I32],
         "arrow_copy": [P, P, I64, P],
         "arrow_profile_enable": [P, I32],
         "arrow_profile_query": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)],
@@ -118,7 +120,8 @@ class _PlanInfo(ctypes.Structure):
                 ("levels", ctypes.c_int32), ("footprint_bytes", ctypes.c_int64),
                 ("chunked_rows", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("upper_rows", ctypes.c_int64), ("contributions", ctypes.c_int64),
-                ("a_inf_norm", ctypes.c_double)]
+                ("a_inf_norm", ctypes.c_double), ("upper_batch", ctypes.c_int32),
+                ("level0_batch", ctypes.c_int32)]
 
 
 class Operand(ctypes.Structure):
@@ -269,6 +272,10 @@ class Plan:
         _check(_load().arrow_plan_info(self._h, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in _PlanInfo._fields_}
 
+    def set_batch(self, kernel: int, batch: int) -> None:
+        """Gather batch of KERNEL_UPPER / KERNEL_LEVEL0: -1 automatic, 0 wide, 4..8 short."""
+        _check(_load().arrow_plan_set_batch(self._h, kernel, batch))
+
     def kernel_bytes(self, kernel: int, k: int, dtype="f32") -> int:
         out = ctypes.c_int64()
         _check(_load().arrow_plan_kernel_bytes(self._h, kernel, k, _dtype_code(dtype),
@@ -375,13 +382,22 @@ def csr_workspace_size(n: int, k: int) -> int:
     return out.value
 
 
-def csr_spmm(n: int, row_ptr, col, val, x, y, sumsq_ws=None, norms=None, stream=None):
+def csr_batch(row_ptr) -> int:
+    """Gather batch for csr_spmm from a host row_ptr (the plan's rule)."""
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    out = ctypes.c_int32()
+    _check(_load().arrow_csr_batch(len(rp) - 1, rp.ctypes.data, ctypes.byref(out)))
+    return out.value
+
+
+def csr_spmm(n: int, row_ptr, col, val, x, y, sumsq_ws=None, norms=None, stream=None, batch=0):
     """Plain CSR baseline on the device (int32 row_ptr / col, FP32 values)."""
     ld = _rows(x, "x")
     if tuple(y.shape) != tuple(x.shape) or _rows(y, "y") != ld:
         raise ValueError("x and y must have the same shape and row stride")
     _check(_load().arrow_csr_spmm(n, _tptr(row_ptr), _tptr(col), _tptr(val), _tptr(x), _tptr(y),
-                                  x.shape[1], ld, _tptr(sumsq_ws), _tptr(norms),
+                                  x.shape[1], ld, batch, _tptr(sumsq_ws), _tptr(norms),
                                   _stream_handle(stream)))
     return y
 

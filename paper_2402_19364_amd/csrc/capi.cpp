@@ -255,6 +255,33 @@ arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out) {
     out->upper_rows = P.n_up;
     out->contributions = P.l0_ncontrib;
     out->a_inf_norm = P.a_inf;
+    out->upper_batch = P.up_batch;
+    out->level0_batch = P.l0_batch;
+    return ARROW_OK;
+}
+
+static bool valid_batch(int32_t batch) {
+    return batch == arrow::kBatchWide || (batch >= arrow::kBatchMin && batch <= arrow::kBatchMax);
+}
+
+arrow_status_t arrow_plan_set_batch(arrow_plan_t p, int32_t kernel, int32_t batch) {
+    if (!p) {
+        set_error("NULL plan");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (kernel != ARROW_KERNEL_UPPER && kernel != ARROW_KERNEL_LEVEL0) {
+        set_error("the gather batch applies to ARROW_KERNEL_UPPER and ARROW_KERNEL_LEVEL0 only");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (batch != -1 && !valid_batch(batch)) {
+        set_error("batch must be -1 (automatic), 0 (wide) or in [4, 8]");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow::Plan &P = *p->p;
+    if (kernel == ARROW_KERNEL_UPPER)
+        P.up_batch = batch == -1 ? P.up_batch_auto : batch;
+    else
+        P.l0_batch = batch == -1 ? P.l0_batch_auto : batch;
     return ARROW_OK;
 }
 
@@ -513,11 +540,29 @@ arrow_status_t arrow_csr_workspace_size(int64_t n, int64_t k, size_t *bytes) {
     return ARROW_OK;
 }
 
+arrow_status_t arrow_csr_batch(int64_t n, const int64_t *row_ptr, int32_t *batch) {
+    if (n < 0 || !batch || (n > 0 && !row_ptr)) {
+        set_error("bad argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    for (int64_t r = 0; r < n; ++r)
+        if (row_ptr[r + 1] < row_ptr[r]) {
+            set_error("row_ptr must be non-decreasing");
+            return ARROW_ERR_INVALID_ARG;
+        }
+    *batch = arrow::choose_batch<int64_t>(n, row_ptr, nullptr);
+    return ARROW_OK;
+}
+
 arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *col,
                               const float *val, const float *x, float *y, int64_t k, int64_t ld,
-                              double *sumsq_ws, double *norms, void *stream) {
+                              int32_t batch, double *sumsq_ws, double *norms, void *stream) {
     if (n < 0 || (n > 0 && !row_ptr)) {
         set_error("bad CSR");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (!valid_batch(batch)) {
+        set_error("batch must be 0 (wide) or in [4, 8]");
         return ARROW_ERR_INVALID_ARG;
     }
     if (arrow_status_t st = check_k(k)) return st;
@@ -527,7 +572,7 @@ arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *
         set_error("x and y must not overlap");
         return ARROW_ERR_INVALID_ARG;
     }
-    return arrow::plain_csr(n, row_ptr, col, val, x, y, k, ld, sumsq_ws, norms,
+    return arrow::plain_csr(n, row_ptr, col, val, x, y, k, ld, batch, sumsq_ws, norms,
                             static_cast<hipStream_t>(stream));
 }
 

@@ -14,6 +14,14 @@ constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
 constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
 constexpr int kStageLists = 1024;    // listed partial rows staged in LDS per block
 constexpr int kChunk = 64;           // entries per chunk of a head row or long row
+// Gather batch of a row pass.  kBatchWide gathers 8 entries of a row per batch
+// and up to 8 listed partial rows at a time; a short batch u in
+// [kBatchMin, kBatchMax] gathers u entries per batch and partial rows 2 at a
+// time, holding fewer registers (more waves per SIMD) for passes whose rows
+// are short.  The batch changes the schedule, not the summation order (the
+// results agree up to the sign of a zero).
+constexpr int kBatchWide = 0;
+constexpr int kBatchMin = 4, kBatchMax = 8;
 
 // One row pass over a CSR-like set of rows.
 struct RowPass {
@@ -28,6 +36,7 @@ struct RowPass {
     const int32_t *cidx;  // rows of the partial buffer
     int32_t b;
     int32_t out_row0;     // first partial-buffer row written by this pass
+    int32_t batch;        // kBatchWide or a short batch in [kBatchMin, kBatchMax]
 };
 
 // One column tile of one operand (all pointers offset to the tile's first column).

@@ -247,14 +247,14 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 // entries of its row from LDS and issues their 8 independent X-row loads
 // before accumulating.  Entries beyond the staged range (a block with more
 // entries than fit) are read from global memory.
-template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32>
+template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH>
 __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) {
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;             // lanes per row
     constexpr int RPW = kWave / LPR;          // rows per wave and round
     constexpr int RPR = RPW * kWaves;         // rows per workgroup and round
-    constexpr int UNR = 8;                    // entries gathered per row and batch
+    constexpr int UNR = BATCH == kBatchWide ? 8 : BATCH;  // entries gathered per row and batch
     static_assert(LPR >= 1 && kWave % LPR == 0, "tile width");
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     using IdxT = typename std::conditional<CODE16, uint16_t, int32_t>::type;
@@ -399,7 +399,8 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                 }
                 if constexpr (CONTRIB) {
                     // listed partial rows (FP32), gathered in batches like the
-                    // entries: 8 wide while more than 2 remain, then 2 wide
+                    // entries: (wide batch) up to 8 at a time while more than 2
+                    // remain, then 2; (short batch) 2 at a time
                     const int c0 = s_cptr[rl] - cb, c1 = s_cptr[rl + 1] - cb;
                     const char *sbase = reinterpret_cast<const char *>(t.s);
                     auto batch = [&](int c, auto width_tag) {
@@ -430,7 +431,8 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                                 acc[4 * q + 3] += __uint_as_float(w.w);
                             }
                     };
-                    constexpr int WIDE = VEC >= 16 ? 2 : (VEC >= 8 ? 4 : 8);
+                    constexpr int WIDE =
+                        BATCH != kBatchWide ? 2 : (VEC >= 16 ? 2 : (VEC >= 8 ? 4 : 8));
                     int c = c0;
                     for (; c1 - c > 2; c += WIDE) batch(c, std::integral_constant<int, WIDE>{});
                     if (c < c1) batch(c, std::integral_constant<int, 2>{});
@@ -752,31 +754,59 @@ __global__ __launch_bounds__(kBlockThreads) void copy_kernel(const vu4 *src, vu4
 
 namespace {
 
-template <int KT, int DT, bool OFF32>
-hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
+template <int KT, int DT, bool OFF32, int BATCH>
+hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const Tile &t,
                         hipStream_t s) {
     dim3 grid(rp.nwg), block(dev::kBlockThreads);
-    if (rp.nwg <= 0) return hipSuccess;
     switch (mode) {
     case kPassChunk:
         hipLaunchKernelGGL((dev::chunk_kernel<KT, DT, OFF32>), grid, block, 0, s, rp, t);
         break;
     case kPassUpper:
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false, OFF32>), grid, block, 0, s, rp, t);
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false, OFF32, BATCH>), grid,
+                           block, 0, s, rp, t);
         break;
     case kPassLevel0:
-        if (code16)
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32>), grid, block, 0, s, rp, t);
-        else
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, true, OFF32>), grid, block, 0, s, rp, t);
+        if (code16) {
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32, BATCH>), grid,
+                               block, 0, s, rp, t);
+        } else {  // int32 columns (b > 21845): wide batches only
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, true, OFF32, kBatchWide>),
+                               grid, block, 0, s, rp, t);
+        }
         break;
-    case kPassPlain:  // plain CSR: int32 columns, no contributions, final store
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, true, OFF32>), grid, block, 0, s, rp, t);
+    case kPassPlain:  // plain CSR (FP32 only): int32 columns, no contributions, final store
+        if constexpr (DT == kF32)
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, true, OFF32, BATCH>), grid,
+                               block, 0, s, rp, t);
+        else
+            return hipErrorInvalidValue;
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Short batches are built for 32-bit offsets only (X spans below 4 GiB);
+// larger operands take the wide batch.
+template <int KT, int DT, bool OFF32>
+hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
+                        hipStream_t s) {
+    if (rp.nwg <= 0) return hipSuccess;
+    if constexpr (OFF32) {
+        if (mode != kPassChunk) {
+            switch (rp.batch) {
+            case 4: return launch_row_b<KT, DT, true, 4>(mode, code16, rp, t, s);
+            case 5: return launch_row_b<KT, DT, true, 5>(mode, code16, rp, t, s);
+            case 6: return launch_row_b<KT, DT, true, 6>(mode, code16, rp, t, s);
+            case 7: return launch_row_b<KT, DT, true, 7>(mode, code16, rp, t, s);
+            case 8: return launch_row_b<KT, DT, true, 8>(mode, code16, rp, t, s);
+            default: break;
+            }
+        }
+    }
+    return launch_row_b<KT, DT, OFF32, kBatchWide>(mode, code16, rp, t, s);
 }
 
 template <int KT, int DT>

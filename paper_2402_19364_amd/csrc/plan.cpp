@@ -79,6 +79,27 @@ static void set_geometry(RowPass &rp, int64_t rows, int rpb, int bpw) {
     rp.nwg = (int32_t)nwg_of(rows, rpb, bpw);
 }
 
+template <class I>
+int32_t choose_batch(int64_t nrows, const I *ptr, const int32_t *cptr) {
+    if (nrows <= 0) return kBatchWide;
+    const int64_t allowed = nrows / 100;  // rows that may need more than one batch
+    if (cptr) {
+        int64_t many = 0;
+        for (int64_t r = 0; r < nrows; ++r) many += (cptr[r + 1] - cptr[r]) > 2;
+        if (many > allowed) return kBatchWide;
+    }
+    int64_t longer[kBatchMax + 1] = {};  // rows with more than u entries
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t len = (int64_t)(ptr[r + 1] - ptr[r]);
+        for (int u = kBatchMin; u <= kBatchMax; ++u) longer[u] += len > u;
+    }
+    for (int u = kBatchMin; u <= kBatchMax; ++u)
+        if (longer[u] <= allowed) return u;
+    return kBatchWide;
+}
+template int32_t choose_batch<int32_t>(int64_t, const int32_t *, const int32_t *);
+template int32_t choose_batch<int64_t>(int64_t, const int64_t *, const int32_t *);
+
 // Partial slots of the final pass (one per workgroup of the level-0 pass).
 static int64_t final_parts(int64_t n) { return nwg_of(n, kRowsPerBlock, kBlocksPerWg); }
 
@@ -215,6 +236,9 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
             l0_cidx[fill[r]++] = (int32_t)s;
         }
     }
+    p.l0_batch = p.l0_batch_auto = choose_batch<int32_t>(n, l0_ptr.data(), l0_cptr.data());
+    p.up_batch = p.up_batch_auto =
+        choose_batch<int32_t>(p.n_up, up_ptr.data(), up_cptr.data());
     p.l0_nnz = (int64_t)l0_val.size();
     p.l0_ncontrib = (int64_t)l0_cidx.size();
     p.up_nnz = (int64_t)up_val.size();
@@ -353,6 +377,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     ch.val = p.ch_val;
     ch.b = p.b;
     ch.out_row0 = (int32_t)p.n_up;
+    ch.batch = kBatchWide;
 
     RowPass upp{};
     set_geometry(upp, p.n_up, kRowsPerBlock, kBlocksPerWg);
@@ -363,6 +388,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.cidx = p.up_cidx;
     upp.b = p.b;
     upp.out_row0 = 0;
+    upp.batch = p.up_batch;
 
     RowPass l0{};
     set_geometry(l0, n, kRowsPerBlock, kBlocksPerWg);
@@ -372,6 +398,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     l0.cptr = p.l0_cptr;
     l0.cidx = p.l0_cidx;
     l0.b = p.b;
+    l0.batch = p.l0_batch;
 
     for (int64_t c0 = 0; c0 < k; c0 += kt) {
         Tile t{};
@@ -450,8 +477,8 @@ size_t plain_csr_workspace(int64_t n, int64_t k) {
 }
 
 arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
-                         const float *x, float *y, int64_t k, int64_t ld, double *ws,
-                         double *norms, hipStream_t s) {
+                         const float *x, float *y, int64_t k, int64_t ld, int32_t batch,
+                         double *ws, double *norms, hipStream_t s) {
     if (n == 0) return ARROW_OK;
     const int kt = tile_width(k);
     const int64_t nb = final_parts(n);
@@ -461,6 +488,7 @@ arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, 
     rp.idx = col;
     rp.val = val;
     rp.b = 0;
+    rp.batch = batch;
     for (int64_t c0 = 0; c0 < k; c0 += kt) {
         Tile t{};
         t.x = x + c0;

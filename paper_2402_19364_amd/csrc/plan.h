@@ -50,6 +50,10 @@ struct Plan {
     // permutation pi_0^{-1}
     int32_t *vop0 = nullptr;
 
+    // gather batch of the upper and level-0 passes (kBatchWide or a short batch)
+    int32_t up_batch = kBatchWide, l0_batch = kBatchWide;
+    int32_t up_batch_auto = kBatchWide, l0_batch_auto = kBatchWide;
+
     int64_t s_rows = 0;  // partial-row buffer rows = n_up + n_chunks
     // distinct X rows each pass reads (algorithmic byte model)
     int64_t distinct_l0 = 0, distinct_up = 0, distinct_ch = 0;
@@ -86,9 +90,16 @@ size_t op_workspace(const Plan &p, int64_t k, int dtype);
 arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s);
 int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype);
 
+// Gather batch for a row pass from its rows' entry counts (ptr, host) and
+// listed partial-row counts (cptr, host, or null): the smallest short batch
+// that holds all entries of at least 99% of the rows, provided at least 99%
+// of the rows list at most 2 partial rows; kBatchWide otherwise.
+template <class I>
+int32_t choose_batch(int64_t nrows, const I *ptr, const int32_t *cptr);
+
 arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
-                         const float *x, float *y, int64_t k, int64_t ld, double *ws,
-                         double *norms, hipStream_t s);
+                         const float *x, float *y, int64_t k, int64_t ld, int32_t batch,
+                         double *ws, double *norms, hipStream_t s);
 size_t plain_csr_workspace(int64_t n, int64_t k);
 
 }  // namespace arrow

@@ -116,6 +116,47 @@ def test_strided_rows_and_hubs():
     _check_trajectory(M, 16, 32, 3, ld=48, label="hubs ld=48")
 
 
+def test_gather_batches_agree():
+    # rows longer than every short batch and rows listing more than 2 partial
+    # rows: each batch must give the same products (the schedule changes, the
+    # summation order does not)
+    M = W.make_matrix("rmat", 12, "row_normalized", 51, 52, 16)
+    d = A_.Decomposition.from_matrix(M, 32, seed=2)
+    plan = A_.Plan(d)
+    inf = plan.info()
+    assert inf["level0_batch"] == 0 and inf["levels"] > 2
+    vop0 = d.level(0)["vop"].astype(np.int64)
+    X0 = W.features(M.n, 32, 4)
+    x = plan.empty(32)
+    plan.permute_in(torch.from_numpy(X0).cuda(), x)
+    base, base_nu, _ = run_steps(plan, x, 2, torch)
+    ref = S.csr_spmm(M, X0.astype(np.float64))
+    for batch in (4, 5, 6, 7, 8, -1):
+        say(f"[parity] rmat12 gather batch {batch}")
+        plan.set_batch(A_.KERNEL_UPPER, batch)
+        plan.set_batch(A_.KERNEL_LEVEL0, batch)
+        ys, nus, _ = run_steps(plan, x, 2, torch)
+        for t in range(2):
+            assert torch.equal(ys[t], base[t]), (batch, t)
+            assert torch.equal(nus[t], base_nu[t]), (batch, t)
+        y0 = plan_order_to_orig(ys[0].cpu().numpy().astype(np.float64), vop0)
+        assert S.rel_fro(y0, ref) <= TOL
+    assert plan.info()["level0_batch"] == inf["level0_batch"]
+    with pytest.raises(A_.ArrowError):
+        plan.set_batch(A_.KERNEL_LEVEL0, 9)
+    with pytest.raises(A_.ArrowError):
+        plan.set_batch(A_.KERNEL_NORM, 5)
+
+
+def test_short_batch_chosen_for_stencils():
+    # identity arrangement with the whole stencil inside the band: one level
+    for shape, size, b, expect in (("grid2d", 24, 40, 5), ("grid3d", 10, 100, 7)):
+        M = W.make_matrix(shape, size, "sym_laplacian", 0, 0)
+        plan = A_.Plan(A_.Decomposition.from_matrix(M, b, seed=1, la=A_.LA_IDENTITY))
+        assert plan.info()["level0_batch"] == expect, shape
+        _check_trajectory(M, b, 16, 2, la=A_.LA_IDENTITY, label=f"{shape} short batch")
+
+
 def test_wide_arrow_int32_codes():
     # b > 21845 switches the level-0 pass to 32-bit columns
     M = W.make_matrix("grid2d", 190, "sym_laplacian", 0, 0)
@@ -141,11 +182,19 @@ def test_plain_csr_baseline():
     y = torch.empty_like(x)
     ws = torch.empty(A_.csr_workspace_size(M.n, 64), dtype=torch.uint8, device="cuda")
     nrm = torch.empty(64, dtype=torch.float64, device="cuda")
-    A_.csr_spmm(M.n, rp, col, val, x, y, sumsq_ws=ws.view(torch.float64), norms=nrm)
-    torch.cuda.synchronize()
     ref = S.csr_spmm(M, X)
-    assert S.rel_fro(y.cpu().numpy(), ref) <= TOL
-    assert np.allclose(nrm.cpu().numpy(), np.linalg.norm(ref, axis=0), rtol=TOL)
+    first = None
+    for batch in (A_.csr_batch(M.row_ptr), 4, 5, 8):
+        A_.csr_spmm(M.n, rp, col, val, x, y, sumsq_ws=ws.view(torch.float64), norms=nrm,
+                    batch=batch)
+        torch.cuda.synchronize()
+        assert S.rel_fro(y.cpu().numpy(), ref) <= TOL
+        assert np.allclose(nrm.cpu().numpy(), np.linalg.norm(ref, axis=0), rtol=TOL)
+        if first is None:
+            first = y.clone()
+        assert torch.equal(y, first), batch
+    with pytest.raises(A_.ArrowError):
+        A_.csr_spmm(M.n, rp, col, val, x, y, batch=3)
 
 
 def test_copy_kernel():

@@ -139,6 +139,23 @@ def test_error_paths():
     assert "max_levels" in msg
 
 
+def test_gather_batch_rule():
+    # smallest short batch (4..8) holding all entries of >= 99% of the rows
+    assert A_.csr_batch(W.make_matrix("grid2d", 30, "uniform", 0, 1).row_ptr) == 5
+    assert A_.csr_batch(W.make_matrix("grid3d", 8, "uniform", 0, 1).row_ptr) == 7
+    assert A_.csr_batch(W.make_matrix("rmat", 12, "row_normalized", 1, 2, 16).row_ptr) == 0
+    assert A_.csr_batch(np.arange(101, dtype=np.int64)) == 4          # one entry per row
+    assert A_.csr_batch(np.zeros(1, dtype=np.int64)) == 0             # no rows
+    lens = np.array([3] * 1000 + [20] * 10)                           # 10 long rows of 1010
+    assert A_.csr_batch(np.concatenate([[0], np.cumsum(lens)])) == 4
+    lens = np.array([3] * 1000 + [20] * 11)                           # 11 of 1011: too many
+    assert A_.csr_batch(np.concatenate([[0], np.cumsum(lens)])) == 0
+    lens = np.array([6] * 990 + [9] * 10)
+    assert A_.csr_batch(np.concatenate([[0], np.cumsum(lens)])) == 6
+    with pytest.raises(A_.ArrowError):
+        A_.csr_batch(np.array([0, 3, 2], dtype=np.int64))
+
+
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "arrow.h")).read()
     declared = set(re.findall(r"\b(arrow_[a-z0-9_]+)\s*\(", hdr))
