@@ -168,7 +168,8 @@ arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);
  * pass's rows when at least 99% of them list at most 2 partial rows, and the
  * wide batch otherwise; batch = -1 restores that choice.  Every batch
  * computes the same sums in the same order (results agree up to the sign of
- * a zero); operands whose X spans 4 GiB or more always take the wide batch.
+ * a zero); operands whose X, or whose partial-row workspace, spans 4 GiB or
+ * more always take the wide batch.
  * Not thread-safe against concurrent products on the same plan.
  */
 arrow_status_t arrow_plan_set_batch(arrow_plan_t p, int32_t kernel, int32_t batch);

@@ -47,6 +47,7 @@ struct Tile {
     const float *s;       // partial-row buffer (FP32), read by the upper / level-0 passes
     float *s_out;         // partial-row buffer written by the chunk / upper passes
     int64_t lds;
+    int64_t s_span;       // bytes from s to the end of the partial-row buffer
     void *y;
     int64_t ldy;
     const float *x_scale;

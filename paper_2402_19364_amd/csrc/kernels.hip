@@ -273,7 +273,8 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     const int sub = lane % LPR;
     const IdxT *gidx = reinterpret_cast<const IdxT *>(rp.idx);
 
-    // X byte offsets fit 32 bits when the matrix spans less than 4 GiB
+    // X and partial-row byte offsets fit 32 bits when both buffers span less
+    // than 4 GiB
     using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
     const char *xbase = reinterpret_cast<const char *>(t.x);
     const Off xstride = (Off)(t.ldx * kElem);
@@ -346,8 +347,11 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
         }
         __syncthreads();
 
-        auto rows = [&](auto staged_tag) {
+        // Block-uniform sources (LDS or global) are compile-time in the row loop,
+        // so no load has to pick its address space at run time.
+        auto rows = [&](auto staged_tag, auto cstaged_tag) {
             constexpr bool STAGED = decltype(staged_tag)::value;
+            constexpr bool CSTAGED = decltype(cstaged_tag)::value;
             for (int rl = wave * RPW + g; rl < nr; rl += RPR) {
                 const int64_t r = row0 + rl;
                 const int a = s_ptr[rl] - e0;
@@ -405,21 +409,25 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                     const char *sbase = reinterpret_cast<const char *>(t.s);
                     auto batch = [&](int c, auto width_tag) {
                         constexpr int W = decltype(width_tag)::value;
-                        uint64_t soff[W];
+                        Off soff[W];
                         bool ok[W];
 #pragma unroll
                         for (int u = 0; u < W; ++u) {
                             ok[u] = c + u < c1;
                             const int cc = ok[u] ? c + u : c;
-                            const int row = cstaged ? s_cidx[cc] : rp.cidx[cb + cc];
-                            soff[u] = ((uint64_t)row * (uint64_t)t.lds + (uint64_t)(sub * VEC)) * 4;
+                            int row;
+                            if constexpr (CSTAGED)
+                                row = s_cidx[cc];
+                            else
+                                row = rp.cidx[cb + cc];
+                            soff[u] = ((Off)row * (Off)t.lds + (Off)(sub * VEC)) * 4;
                         }
                         vu4 sv[W][VEC / 4];
 #pragma unroll
                         for (int u = 0; u < W; ++u)
 #pragma unroll
                             for (int q = 0; q < VEC / 4; ++q)
-                                sv[u][q] = load16(sbase, soff[u] + (uint64_t)(16 * q));
+                                sv[u][q] = load16(sbase, soff[u] + (Off)(16 * q));
 #pragma unroll
                         for (int u = 0; u < W; ++u)
 #pragma unroll
@@ -458,10 +466,24 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                 }
             }
         };
-        if (staged)
-            rows(std::true_type{});
-        else
-            rows(std::false_type{});
+        if constexpr (CONTRIB) {
+            if (staged) {
+                if (cstaged)
+                    rows(std::true_type{}, std::true_type{});
+                else
+                    rows(std::true_type{}, std::false_type{});
+            } else {
+                if (cstaged)
+                    rows(std::false_type{}, std::true_type{});
+                else
+                    rows(std::false_type{}, std::false_type{});
+            }
+        } else {
+            if (staged)
+                rows(std::true_type{}, std::true_type{});
+            else
+                rows(std::false_type{}, std::true_type{});
+        }
     }
 
     if constexpr (FINAL) {
@@ -788,8 +810,8 @@ hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const Tile &t,
     return hipGetLastError();
 }
 
-// Short batches are built for 32-bit offsets only (X spans below 4 GiB);
-// larger operands take the wide batch.
+// Short batches are built for 32-bit offsets only (X and the partial-row
+// buffer below 4 GiB); larger operands take the wide batch.
 template <int KT, int DT, bool OFF32>
 hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
                         hipStream_t s) {
@@ -811,7 +833,7 @@ hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
 
 template <int KT, int DT>
 hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const Tile &t, hipStream_t s) {
-    if (t.x_span < (int64_t(1) << 32))
+    if (t.x_span < (int64_t(1) << 32) && t.s_span < (int64_t(1) << 32))
         return launch_row_o<KT, DT, true>(mode, code16, rp, t, s);
     return launch_row_o<KT, DT, false>(mode, code16, rp, t, s);
 }

@@ -408,6 +408,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
         t.s = sbuf + c0;
         t.s_out = sbuf + c0;
         t.lds = k;
+        t.s_span = (p.s_rows * k - c0) * 4;
         t.y = static_cast<char *>(op.y) + c0 * es;
         t.ldy = op.ldy;
         t.x_scale = op.x_scale ? op.x_scale + c0 : nullptr;
