@@ -149,11 +149,14 @@ typedef struct {
     int64_t footprint_bytes;  /* device memory owned by the plan */
     int64_t chunked_rows;     /* rows split into nnz chunks (the head rows and long rows) */
     int64_t chunks;           /* number of chunks */
-    int64_t upper_rows;       /* rows of levels >= 1 that hold entries */
+    int64_t upper_rows;       /* rows of levels >= 1 computed by the upper pass */
     int64_t contributions;    /* summands gathered by the level-0 pass */
     double a_inf_norm;        /* max_i sum_j |A_ij| (bounds the FP8/FP16 scales) */
     int32_t upper_batch;      /* gather batch of the upper / level-0 passes: 0 = wide, */
     int32_t level0_batch;     /* else entries gathered per row and batch (4..8) */
+    int64_t fused_rows;       /* rows of levels >= 1 folded into their level-0 row */
+    int32_t level0_block_rows; /* rows per staged block of the level-0 pass */
+    int32_t reserved;
 } arrow_plan_info_t;
 
 arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);

@@ -121,7 +121,8 @@ class _PlanInfo(ctypes.Structure):
                 ("chunked_rows", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("upper_rows", ctypes.c_int64), ("contributions", ctypes.c_int64),
                 ("a_inf_norm", ctypes.c_double), ("upper_batch", ctypes.c_int32),
-                ("level0_batch", ctypes.c_int32)]
+                ("level0_batch", ctypes.c_int32), ("fused_rows", ctypes.c_int64),
+                ("level0_block_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Operand(ctypes.Structure):

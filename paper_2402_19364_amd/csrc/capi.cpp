@@ -257,6 +257,9 @@ arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out) {
     out->a_inf_norm = P.a_inf;
     out->upper_batch = P.up_batch;
     out->level0_batch = P.l0_batch;
+    out->fused_rows = P.fused_rows;
+    out->level0_block_rows = P.l0_rpb;
+    out->reserved = 0;
     return ARROW_OK;
 }
 

@@ -12,7 +12,7 @@ enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
 constexpr int kNumXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
 constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
-constexpr int kStageLists = 1024;    // listed partial rows staged in LDS per block
+constexpr int kStageLists = 512;     // listed partial rows staged in LDS per block
 constexpr int kChunk = 64;           // entries per chunk of a head row or long row
 // Gather batch of a row pass.  kBatchWide gathers 8 entries of a row per batch
 // and up to 8 listed partial rows at a time; a short batch u in
@@ -34,6 +34,13 @@ struct RowPass {
     const float *val;
     const int32_t *cptr;  // [nrows + 1] listed partial rows (or null when unused)
     const int32_t *cidx;  // rows of the partial buffer
+    // level-0 pass with 16-bit codes: code 3b+1+j names entry j of the block's
+    // far-column table fcol[fptr[block] ...]; fpos gives the entry's index
+    // within the block, so a staged block scatters the table next to its
+    // entries in LDS (null: no far entries)
+    const int32_t *fptr;
+    const int32_t *fcol;
+    const uint16_t *fpos;
     int32_t b;
     int32_t out_row0;     // first partial-buffer row written by this pass
     int32_t batch;        // kBatchWide or a short batch in [kBatchMin, kBatchMax]

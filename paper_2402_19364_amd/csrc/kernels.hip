@@ -247,7 +247,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 // entries of its row from LDS and issues their 8 independent X-row loads
 // before accumulating.  Entries beyond the staged range (a block with more
 // entries than fit) are read from global memory.
-template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH>
+template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR>
 __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) {
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
@@ -264,6 +264,9 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     __shared__ int32_t s_cidx[CONTRIB ? kStageLists : 1];
     __shared__ IdxT s_idx[kStageEntries];
     __shared__ float s_val[kStageEntries];
+    // far columns of the staged entries (valid where the code is a far code)
+    __shared__ int32_t s_fcol[FAR ? kStageEntries : 1];
+    __shared__ int32_t s_fb[2];
 
     const int wg = xcd_block(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
@@ -323,16 +326,28 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
             s_ptr[i] = rp.ptr[row0 + i];
             if constexpr (CONTRIB) s_cptr[i] = rp.cptr[row0 + i];
         }
+        if constexpr (FAR) {
+            if (tid < 2) s_fb[tid] = rp.fptr[row0 / rp.rows_per_block + tid];
+        }
         __syncthreads();
         const int e0 = s_ptr[0];
         const int ne = s_ptr[nr] - e0;
         // Block-uniform choice: the block's entries come from LDS when they fit,
         // otherwise every entry is read from global memory.
         const bool staged = ne <= kStageEntries;
+        int fb = 0;
+        if constexpr (FAR) fb = s_fb[0];
         if (staged) {
             for (int i = tid; i < ne; i += kBlockThreads) {
                 s_idx[i] = gidx[e0 + i];
                 s_val[i] = rp.val[e0 + i];
+            }
+            if constexpr (FAR) {
+                const int nf = s_fb[1] - fb;  // <= ne, every fpos < ne
+                for (int i = tid; i < nf; i += kBlockThreads) {
+                    const int pos = rp.fpos[fb + i];
+                    s_fcol[pos < kStageEntries ? pos : kStageEntries - 1] = rp.fcol[fb + i];
+                }
             }
         }
         // the block's list of partial rows, staged the same way
@@ -364,8 +379,9 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                     // padding slots of the last batch re-read the batch's first
                     // entry (a valid address) and contribute an exact zero
                     float av[UNR];
-                    Off off[UNR];
+                    int col[UNR];
                     bool ok[UNR];
+                    bool anyfar = false;
 #pragma unroll
                     for (int u = 0; u < UNR; ++u) {
                         ok[u] = e + u < len;
@@ -380,15 +396,42 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                             v = rp.val[e0 + ee];
                         }
                         av[u] = ok[u] ? v : 0.0f;
-                        int c;
                         if constexpr (CODE16) {
+                            // band (<= 2b), head column (<= 3b), or entry j of the
+                            // block's far-column table (3b+1+j)
                             const int cc = code;
-                            c = cc <= 2 * rp.b ? rb + cc : cc - 2 * rp.b - 1;
+                            col[u] = cc <= 2 * rp.b ? rb + cc : cc - 2 * rp.b - 1;
+                            if constexpr (FAR) anyfar |= cc > 3 * rp.b;
                         } else {
-                            c = code;
+                            col[u] = code;
                         }
-                        off[u] = (Off)c * xstride + xlane;
                     }
+                    if constexpr (FAR) {
+                        // the batch's folded entries (waves whose batch has none
+                        // skip this): a staged block scattered their columns beside
+                        // the codes; otherwise the block's table is read directly
+                        // (index clamped to the table's first entry, which exists
+                        // since the wave's batch holds a far code)
+                        if (__builtin_amdgcn_ballot_w64(anyfar)) {
+#pragma unroll
+                            for (int u = 0; u < UNR; ++u) {
+                                const int ee = a + (ok[u] ? e + u : e);
+                                int cc, far;
+                                if constexpr (STAGED) {
+                                    cc = s_idx[ee];
+                                    far = s_fcol[ee];
+                                } else {
+                                    cc = gidx[e0 + ee];
+                                    const int fi = cc - 3 * rp.b - 1;
+                                    far = rp.fcol[fb + (fi > 0 ? fi : 0)];
+                                }
+                                col[u] = cc > 3 * rp.b ? far : col[u];
+                            }
+                        }
+                    }
+                    Off off[UNR];
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) off[u] = (Off)col[u] * xstride + xlane;
                     typename F::Raw xr[UNR];
 #pragma unroll
                     for (int u = 0; u < UNR; ++u) xr[u] = loadw<typename F::Raw>(xbase, off[u]);
@@ -785,22 +828,27 @@ hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const Tile &t,
         hipLaunchKernelGGL((dev::chunk_kernel<KT, DT, OFF32>), grid, block, 0, s, rp, t);
         break;
     case kPassUpper:
-        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false, OFF32, BATCH>), grid,
-                           block, 0, s, rp, t);
+        hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, false, OFF32, BATCH, false>),
+                           grid, block, 0, s, rp, t);
         break;
     case kPassLevel0:
-        if (code16) {
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32, BATCH>), grid,
-                               block, 0, s, rp, t);
-        } else {  // int32 columns (b > 21845): wide batches only
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, true, true, OFF32, kBatchWide>),
+        if (code16 && rp.fptr) {  // with folded entries of levels >= 1
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32, BATCH, true>),
                                grid, block, 0, s, rp, t);
+        } else if (code16) {
+            hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32, BATCH, false>),
+                               grid, block, 0, s, rp, t);
+        } else {  // int32 columns (b > 21845): wide batches only
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, false, true, true, OFF32, kBatchWide, false>), grid,
+                block, 0, s, rp, t);
         }
         break;
     case kPassPlain:  // plain CSR (FP32 only): int32 columns, no contributions, final store
         if constexpr (DT == kF32)
-            hipLaunchKernelGGL((dev::row_kernel<KT, DT, false, false, true, OFF32, BATCH>), grid,
-                               block, 0, s, rp, t);
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, false, false, true, OFF32, BATCH, false>), grid, block,
+                0, s, rp, t);
         else
             return hipErrorInvalidValue;
         break;

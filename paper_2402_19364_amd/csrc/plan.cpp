@@ -101,7 +101,8 @@ template int32_t choose_batch<int32_t>(int64_t, const int32_t *, const int32_t *
 template int32_t choose_batch<int64_t>(int64_t, const int64_t *, const int32_t *);
 
 // Partial slots of the final pass (one per workgroup of the level-0 pass).
-static int64_t final_parts(int64_t n) { return nwg_of(n, kRowsPerBlock, kBlocksPerWg); }
+static int64_t final_parts(int64_t n, int64_t rpb) { return nwg_of(n, rpb, kBlocksPerWg); }
+static int64_t final_parts(const Plan &p) { return final_parts(p.n, p.l0_rpb); }
 
 arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out) {
     out = nullptr;
@@ -133,14 +134,98 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         for (double v : rs) p.a_inf = std::max(p.a_inf, v);
     }
 
-    // upper rows (levels >= 1 with entries), in (level, position) order
+    // rows of levels >= 1 that hold entries, grouped by the level-0 row of
+    // their vertex (level order within a vertex); `order` keeps (level, pos)
     struct UpRow { int32_t level; int32_t pos; };
-    std::vector<UpRow> up;
+    auto up_len = [&](const UpRow &u) -> int64_t {
+        const Level &L = d.levels[u.level];
+        return L.row_ptr[u.pos + 1] - L.row_ptr[u.pos];
+    };
+    std::vector<int64_t> vrow_ptr(n + 1, 0);
     for (int32_t i = 1; i < p.levels; ++i) {
         const Level &L = d.levels[i];
         for (int64_t q = 0; q < L.n_i; ++q)
-            if (L.row_ptr[q + 1] > L.row_ptr[q]) up.push_back({i, (int32_t)q});
+            if (L.row_ptr[q + 1] > L.row_ptr[q]) ++vrow_ptr[pos0[L.vop[q]] + 1];
     }
+    for (int64_t r = 0; r < n; ++r) vrow_ptr[r + 1] += vrow_ptr[r];
+    std::vector<UpRow> vrows(vrow_ptr[n]);
+    std::vector<int64_t> order;  // indices into vrows, in (level, position) order
+    order.reserve(vrows.size());
+    {
+        std::vector<int64_t> fill(vrow_ptr.begin(), vrow_ptr.end() - 1);
+        for (int32_t i = 1; i < p.levels; ++i) {
+            const Level &L = d.levels[i];
+            for (int64_t q = 0; q < L.n_i; ++q)
+                if (L.row_ptr[q + 1] > L.row_ptr[q]) {
+                    const int64_t si = fill[pos0[L.vop[q]]]++;
+                    vrows[si] = {i, (int32_t)q};
+                    order.push_back(si);
+                }
+        }
+    }
+
+    // level-0 rows of the chunk pass: head rows of B_0 and long rows
+    std::vector<uint8_t> chunked0(n, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t len = L0.row_ptr[r + 1] - L0.row_ptr[r];
+        chunked0[r] = (r < b && len > 0) || len > kLongRow;
+    }
+
+    // Level-0 block size: the largest of 256, 128, 64 rows for which 95% of
+    // the blocks' entries (level 0 plus the short rows that may fold in) fit
+    // the LDS staging area.
+    p.l0_rpb = kMaxBlockRows;
+    for (int rpb = kMaxBlockRows; rpb >= 64; rpb /= 2) {
+        p.l0_rpb = rpb;
+        const int64_t nblk = nblocks_of(n, rpb);
+        int64_t over = 0;
+        for (int64_t blk = 0; blk < nblk; ++blk) {
+            int64_t ne = 0;
+            for (int64_t r = blk * rpb; r < std::min<int64_t>(n, (blk + 1) * rpb); ++r) {
+                if (chunked0[r]) continue;
+                ne += L0.row_ptr[r + 1] - L0.row_ptr[r];
+                for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si) {
+                    const int64_t ul = up_len(vrows[si]);
+                    if (ul <= kLongRow) ne += ul;
+                }
+            }
+            over += ne > kStageEntries;
+        }
+        if (over * 20 <= nblk) break;
+    }
+    const int64_t rpb0 = p.l0_rpb;
+
+    // Cross-level accumulation at entry level: a short row of a level >= 1
+    // joins the entry list of its vertex's level-0 row (columns mapped through
+    // sigma_i), as long as the row stays within kFuseRow entries and the
+    // 16-bit codes 3b+1+j of the block's far-column table have room.  The
+    // rest keep the upper pass and reach the level-0 row as partial rows.
+    const int64_t far_cap = p.code16 ? 65535 - 3 * (int64_t)b : INT64_MAX;
+    std::vector<uint8_t> fused(vrows.size(), 0);
+    for (int64_t blk = 0; blk < nblocks_of(n, rpb0); ++blk) {
+        int64_t far = 0;
+        for (int64_t r = blk * rpb0; r < std::min<int64_t>(n, (blk + 1) * rpb0); ++r) {
+            if (chunked0[r]) continue;
+            int64_t len = L0.row_ptr[r + 1] - L0.row_ptr[r];
+            for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si) {
+                const int64_t ul = up_len(vrows[si]);
+                if (ul > kLongRow || len + ul > kFuseRow || far + ul > far_cap) continue;
+                fused[si] = 1;
+                len += ul;
+                far += ul;
+                ++p.fused_rows;
+            }
+        }
+    }
+
+    // upper rows: the rows of levels >= 1 not folded in, in (level, position) order
+    std::vector<UpRow> up;
+    std::vector<int64_t> up_of(vrows.size(), -1);  // vrows index -> upper row
+    for (int64_t si : order)
+        if (!fused[si]) {
+            up_of[si] = (int64_t)up.size();
+            up.push_back(vrows[si]);
+        }
     p.n_up = (int64_t)up.size();
 
     // chunks: level-0 chunked rows, then chunked upper rows
@@ -165,11 +250,14 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     std::vector<uint16_t> l0_code;
     std::vector<int32_t> l0_col;
     std::vector<float> l0_val;
+    std::vector<int32_t> far_ptr(nblocks_of(n, rpb0) + 1, 0), far_col;
+    std::vector<uint16_t> far_pos;  // entry index of each far entry within its block
     std::vector<uint8_t> seen_l0(n, 0), seen_up(n, 0), seen_ch(n, 0);
     for (int64_t r = 0; r < n; ++r) {
+        const int64_t blk = r / rpb0;
+        if (r % rpb0 == 0) far_ptr[blk] = (int32_t)far_col.size();
         const int64_t e0 = L0.row_ptr[r], e1 = L0.row_ptr[r + 1];
-        const bool chunked = (r < b && e1 > e0) || (e1 - e0 > kLongRow);
-        if (chunked) {
+        if (chunked0[r]) {
             auto fc = add_chunks(L0, r, false);
             l0_chunk_first[r] = fc.first;
             l0_chunk_count[r] = fc.second;
@@ -186,9 +274,30 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
                 l0_val.push_back(L0.val[e]);
                 seen_l0[q] = 1;
             }
+            for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si) {
+                if (!fused[si]) continue;
+                const Level &L = d.levels[vrows[si].level];
+                const int64_t q = vrows[si].pos;
+                for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e) {
+                    const int32_t c = pos0[L.vop[L.col[e]]];
+                    if (p.code16) {
+                        const int64_t j = (int64_t)far_col.size() - far_ptr[blk];
+                        far_pos.push_back((uint16_t)((int64_t)l0_val.size() -
+                                                     l0_ptr[blk * rpb0]));
+                        l0_code.push_back((uint16_t)(3 * (int64_t)b + 1 + j));
+                        far_col.push_back(c);
+                    } else {
+                        l0_col.push_back(c);
+                    }
+                    l0_val.push_back(L.val[e]);
+                    seen_l0[c] = 1;
+                }
+            }
         }
         l0_ptr[r + 1] = (int32_t)l0_val.size();
     }
+    far_ptr[nblocks_of(n, rpb0)] = (int32_t)far_col.size();
+    p.l0_nfar = (int64_t)far_col.size();
     std::vector<int32_t> up_ptr(p.n_up + 1, 0), up_col, up_cptr(p.n_up + 1, 0), up_cidx;
     std::vector<float> up_val;
     std::vector<std::pair<int32_t, int32_t>> up_chunks(p.n_up, {-1, 0});
@@ -218,23 +327,15 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
             up_cidx.push_back((int32_t)(p.n_up + up_chunks[s].first + c));
         up_cptr[s + 1] = (int32_t)up_cidx.size();
     }
-    // partial rows listed by the level-0 rows: own chunks, then upper rows by level
+    // partial rows listed by the level-0 rows: own chunks, then the upper rows
+    // of the same vertex by level
     std::vector<int32_t> l0_cptr(n + 1, 0), l0_cidx;
-    {
-        std::vector<int32_t> cnt(n, 0);
-        for (int64_t r = 0; r < n; ++r) cnt[r] = l0_chunk_count[r];
-        for (int64_t s = 0; s < p.n_up; ++s)
-            ++cnt[pos0[d.levels[up[s].level].vop[up[s].pos]]];
-        for (int64_t r = 0; r < n; ++r) l0_cptr[r + 1] = l0_cptr[r] + cnt[r];
-        l0_cidx.assign(l0_cptr[n], 0);
-        std::vector<int32_t> fill(l0_cptr.begin(), l0_cptr.end() - 1);
-        for (int64_t r = 0; r < n; ++r)
-            for (int32_t c = 0; c < l0_chunk_count[r]; ++c)
-                l0_cidx[fill[r]++] = (int32_t)(p.n_up + l0_chunk_first[r] + c);
-        for (int64_t s = 0; s < p.n_up; ++s) {
-            const int32_t r = pos0[d.levels[up[s].level].vop[up[s].pos]];
-            l0_cidx[fill[r]++] = (int32_t)s;
-        }
+    for (int64_t r = 0; r < n; ++r) {
+        for (int32_t c = 0; c < l0_chunk_count[r]; ++c)
+            l0_cidx.push_back((int32_t)(p.n_up + l0_chunk_first[r] + c));
+        for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si)
+            if (!fused[si]) l0_cidx.push_back((int32_t)up_of[si]);
+        l0_cptr[r + 1] = (int32_t)l0_cidx.size();
     }
     p.l0_batch = p.l0_batch_auto = choose_batch<int32_t>(n, l0_ptr.data(), l0_cptr.data());
     p.up_batch = p.up_batch_auto =
@@ -270,6 +371,11 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     UP(p.l0_val, l0_val);
     UP(p.l0_cptr, l0_cptr);
     UP(p.l0_cidx, l0_cidx);
+    if (p.l0_nfar > 0) {
+        UP(p.l0_fptr, far_ptr);
+        UP(p.l0_fcol, far_col);
+        UP(p.l0_fpos, far_pos);
+    }
     UP(p.up_ptr, up_ptr);
     UP(p.up_col, up_col);
     UP(p.up_val, up_val);
@@ -309,7 +415,7 @@ void plan_destroy(Plan *p) {
 
 size_t op_workspace(const Plan &p, int64_t k, int dtype) {
     (void)dtype;
-    const int64_t nb = final_parts(p.n);
+    const int64_t nb = final_parts(p);
     return align256((size_t)p.s_rows * k * 4) + align256((size_t)k * nb * 8) +
            align256((size_t)k * nb * 4);
 }
@@ -362,7 +468,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     if (n == 0) return ARROW_OK;
     const int kt = tile_width(k);
     const int64_t es = elem_size(op.dtype);
-    const int64_t nb = final_parts(n);
+    const int64_t nb = final_parts(p);
     char *w = static_cast<char *>(ws);
     float *sbuf = reinterpret_cast<float *>(w);
     w += align256((size_t)p.s_rows * k * 4);
@@ -391,12 +497,15 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.batch = p.up_batch;
 
     RowPass l0{};
-    set_geometry(l0, n, kRowsPerBlock, kBlocksPerWg);
+    set_geometry(l0, n, p.l0_rpb, kBlocksPerWg);
     l0.ptr = p.l0_ptr;
     l0.idx = p.l0_idx;
     l0.val = p.l0_val;
     l0.cptr = p.l0_cptr;
     l0.cidx = p.l0_cidx;
+    l0.fptr = p.l0_fptr;
+    l0.fcol = p.l0_fcol;
+    l0.fpos = p.l0_fpos;
     l0.b = p.b;
     l0.batch = p.l0_batch;
 
@@ -449,7 +558,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
 
 int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
     const int64_t sx = elem_size(dtype);
-    const int64_t nb = final_parts(p.n);
+    const int64_t nb = final_parts(p);
     const bool scaled = dtype == kF16 || dtype == kF8E4M3;
     switch (kernel) {
     case ARROW_KERNEL_CHUNKS:
@@ -461,6 +570,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
                p.distinct_up * k * sx + p.n_up * k * 4;
     case ARROW_KERNEL_LEVEL0:
         return p.l0_nnz * ((p.code16 ? 2 : 4) + 4) + (p.n + 1) * 8 +
+               (p.l0_nfar > 0 ? p.l0_nfar * 6 + (nblocks_of(p.n, p.l0_rpb) + 1) * 4 : 0) +
                p.l0_ncontrib * (4 + k * 4) + p.distinct_l0 * k * sx + p.n * k * sx +
                nb * k * (8 + (scaled ? 4 : 0)) + k * (scaled ? 16 : 8);
     case ARROW_KERNEL_NORM:
@@ -473,7 +583,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
 }
 
 size_t plain_csr_workspace(int64_t n, int64_t k) {
-    const int64_t nb = final_parts(n);
+    const int64_t nb = final_parts(n, kRowsPerBlock);
     return align256((size_t)k * nb * 8);
 }
 
@@ -482,7 +592,7 @@ arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, 
                          double *ws, double *norms, hipStream_t s) {
     if (n == 0) return ARROW_OK;
     const int kt = tile_width(k);
-    const int64_t nb = final_parts(n);
+    const int64_t nb = final_parts(n, kRowsPerBlock);
     RowPass rp{};
     set_geometry(rp, n, kRowsPerBlock, kBlocksPerWg);
     rp.ptr = row_ptr;

@@ -12,6 +12,7 @@
 namespace arrow {
 
 constexpr int kLongRow = 32;      // rows with more entries go through the chunk pass
+constexpr int kFuseRow = 32;      // longest level-0 row after folding in rows of levels >= 1
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
 constexpr int kBlocksPerWg = 4;                    // blocks walked by one workgroup
 constexpr int kChunksPerBlock = 4;                // chunks per workgroup (one per wave)
@@ -36,6 +37,12 @@ struct Plan {
     int32_t *l0_cptr = nullptr;
     int32_t *l0_cidx = nullptr;
     int64_t l0_nnz = 0, l0_ncontrib = 0;
+    int32_t l0_rpb = kMaxBlockRows;     // rows per staged block of the level-0 pass
+    int32_t *l0_fptr = nullptr;         // [blocks + 1] far-column table of each block
+    int32_t *l0_fcol = nullptr;         // pi_0 columns of entries folded in from levels >= 1
+    uint16_t *l0_fpos = nullptr;        // their entry index within the block
+    int64_t l0_nfar = 0;                // entries in the far-column tables
+    int64_t fused_rows = 0;             // rows of levels >= 1 folded into level-0 rows
     // upper pass (rows of levels >= 1 with entries)
     int64_t n_up = 0;
     int32_t *up_ptr = nullptr, *up_col = nullptr;
