@@ -170,9 +170,10 @@ arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);
  * the smallest short batch that holds the entries of at least 99% of the
  * pass's rows when at least 99% of them list at most 2 partial rows, and the
  * wide batch otherwise; batch = -1 restores that choice.  Every batch
- * computes the same sums in the same order (results agree up to the sign of
- * a zero); operands whose X, or whose partial-row workspace, spans 4 GiB or
- * more always take the wide batch.
+ * computes the same products in the same order (they agree up to the sign of
+ * a zero); the FP64 column norms reduce the same squares in a batch-dependent
+ * fixed order, so they agree to rounding.  Operands whose X, or whose
+ * partial-row workspace, spans 4 GiB or more always take the wide batch.
  * Not thread-safe against concurrent products on the same plan.
  */
 arrow_status_t arrow_plan_set_batch(arrow_plan_t p, int32_t kernel, int32_t batch);
@@ -289,7 +290,7 @@ arrow_status_t arrow_csr_workspace_size(int64_t n, int64_t k, size_t *bytes);
  * rule arrow_plan_create applies to its passes (0 = wide, else 4..8). */
 arrow_status_t arrow_csr_batch(int64_t n, const int64_t *row_ptr, int32_t *batch);
 /* batch: 0 (wide) or 4..8 entries gathered per row and batch (a schedule
- * choice: every batch gives the same result). */
+ * choice: every batch gives the same y; the norms agree to rounding). */
 arrow_status_t arrow_csr_spmm(int64_t n, const int32_t *row_ptr, const int32_t *col,
                               const float *val, const float *x, float *y, int64_t k, int64_t ld,
                               int32_t batch, double *sumsq_ws, double *norms, void *stream);

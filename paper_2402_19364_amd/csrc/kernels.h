@@ -18,8 +18,9 @@ constexpr int kChunk = 64;           // entries per chunk of a head row or long 
 // and up to 8 listed partial rows at a time; a short batch u in
 // [kBatchMin, kBatchMax] gathers u entries per batch and partial rows 2 at a
 // time, holding fewer registers (more waves per SIMD) for passes whose rows
-// are short.  The batch changes the schedule, not the summation order (the
-// results agree up to the sign of a zero).
+// are short.  The batch changes the schedule, not the summation order of a
+// product (results agree up to the sign of a zero); the column sums of
+// squares are reduced in a batch-dependent fixed order.
 constexpr int kBatchWide = 0;
 constexpr int kBatchMin = 4, kBatchMax = 8;
 

@@ -283,36 +283,51 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
     const Off xstride = (Off)(t.ldx * kElem);
     const Off xlane = (Off)(sub * F::kBytes);
 
-    // per-column factors of the final pass (this lane's VEC columns)
-    // Output scale of column j for the scaled formats: the power of two c_j with
-    // |Y[:, j]| <= ||A||_inf * x_scale_j * max|code_j| * (1/nu_j) <= c_j * max.
-    auto out_scale = [&](int j) -> float {
-        const float xs = t.x_scale ? t.x_scale[j] : 1.0f;
-        const double inv = t.x_inv_norm ? t.x_inv_norm[j] : 1.0;
-        const float xm = t.x_maxabs ? t.x_maxabs[j] : F::kMax;
-        return pow2_ceil((double)t.a_inf * (double)xs * (double)xm * inv / (double)F::kMax);
-    };
-    // mul = x_scale * (1/nu) / c (c exact power of two); sums of squares are
-    // kept in code units and scaled by c^2 once at the end (exact)
-    float mul[VEC];
-    double ssq[VEC];
-    float cmax[F::kScaled ? VEC : 1];
+    // Per-column state of the final pass, in LDS (registers stay free for the
+    // gathers): mul_j = x_scale_j * (1/nu_j) / c_j, the output scale c_j (a
+    // power of two; 1 for unscaled formats) and, per wave, running FP64 sums
+    // of squares and max |code| of the stored values in code units (scaled by
+    // c_j^2 once at the end, exactly).  For the scaled formats c_j is the
+    // power of two with |Y[:, j]| <= ||A||_inf x_scale_j max|code_j| / nu_j
+    // <= c_j * max.
+    // Short batches keep the lane's own columns' factors and sums in registers
+    // (a butterfly once at the end); the wide batch, short of registers, keeps
+    // them in LDS and reduces the row groups every round.
+    constexpr bool LDS_SUMS = BATCH == kBatchWide;
+    __shared__ float s_mul[FINAL ? KT : 1];
+    __shared__ float s_c[FINAL ? KT : 1];
+    __shared__ double s_ssq[FINAL ? kWaves : 1][FINAL ? KT : 1];
+    __shared__ float s_max[FINAL ? kWaves : 1][FINAL ? KT : 1];
+    float mul[LDS_SUMS ? 1 : VEC];
+    double ssq[LDS_SUMS ? 1 : VEC];
+    float cmax[LDS_SUMS ? 1 : VEC];
     if constexpr (FINAL) {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            const int j = sub * VEC + i;
+        for (int j = tid; j < KT; j += kBlockThreads) {
             const float xs = t.x_scale ? t.x_scale[j] : 1.0f;
             const double inv = t.x_inv_norm ? t.x_inv_norm[j] : 1.0;
             const float fac = (float)((double)xs * inv);
+            float c = 1.0f;
             if constexpr (F::kScaled) {
-                const float c = out_scale(j);
-                mul[i] = fac * (1.0f / c);
-                cmax[i] = 0.0f;
-                if (wg == 0 && wave == 0 && g == 0 && t.y_scale) t.y_scale[j] = c;
-            } else {
-                mul[i] = fac;
+                const float xm = t.x_maxabs ? t.x_maxabs[j] : F::kMax;
+                c = pow2_ceil((double)t.a_inf * (double)xs * (double)xm * inv /
+                              (double)F::kMax);
+                if (wg == 0 && t.y_scale) t.y_scale[j] = c;
             }
-            ssq[i] = 0.0;
+            s_mul[j] = fac * (1.0f / c);
+            s_c[j] = c;
+        }
+        for (int i = tid; i < kWaves * KT; i += kBlockThreads) {
+            s_ssq[i / KT][i % KT] = 0.0;
+            s_max[i / KT][i % KT] = 0.0f;
+        }
+        __syncthreads();
+        if constexpr (!LDS_SUMS) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                mul[i] = s_mul[sub * VEC + i];
+                ssq[i] = 0.0;
+                cmax[i] = 0.0f;
+            }
         }
     }
 
@@ -367,10 +382,15 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
         auto rows = [&](auto staged_tag, auto cstaged_tag) {
             constexpr bool STAGED = decltype(staged_tag)::value;
             constexpr bool CSTAGED = decltype(cstaged_tag)::value;
-            for (int rl = wave * RPW + g; rl < nr; rl += RPR) {
+            // wave-uniform trip count: the final pass reduces across the
+            // wave's row groups every round (rows past the block end are idle)
+            for (int rbase = wave * RPW; rbase < nr; rbase += RPR) {
+                const int rl = rbase + g;
+                const bool live = rl < nr;
+                const int rs = live ? rl : nr - 1;  // an idle group reads a valid row...
                 const int64_t r = row0 + rl;
-                const int a = s_ptr[rl] - e0;
-                const int len = s_ptr[rl + 1] - e0 - a;
+                const int a = s_ptr[rs] - e0;
+                const int len = live ? s_ptr[rs + 1] - e0 - a : 0;  // ...and gathers nothing
                 const int rb = (int)r - rp.b;  // band start (16-bit codes)
                 float acc[VEC];
 #pragma unroll
@@ -448,7 +468,7 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                     // listed partial rows (FP32), gathered in batches like the
                     // entries: (wide batch) up to 8 at a time while more than 2
                     // remain, then 2; (short batch) 2 at a time
-                    const int c0 = s_cptr[rl] - cb, c1 = s_cptr[rl + 1] - cb;
+                    const int c0 = s_cptr[rs] - cb, c1 = live ? s_cptr[rs + 1] - cb : c0;
                     const char *sbase = reinterpret_cast<const char *>(t.s);
                     auto batch = [&](int c, auto width_tag) {
                         constexpr int W = decltype(width_tag)::value;
@@ -488,19 +508,46 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                     for (; c1 - c > 2; c += WIDE) batch(c, std::integral_constant<int, WIDE>{});
                     if (c < c1) batch(c, std::integral_constant<int, 2>{});
                 }
-                if constexpr (FINAL) {
+                if constexpr (FINAL && !LDS_SUMS) {
+                    if (live) {
 #pragma unroll
-                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * mul[i];
-                    char *yp =
-                        reinterpret_cast<char *>(t.y) + r * t.ldy * kElem + (int64_t)sub * F::kBytes;
-                    F::store(yp, acc);  // acc now holds the stored (rounded) codes as floats
+                        for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * mul[i];
+                        char *yp = reinterpret_cast<char *>(t.y) + r * t.ldy * kElem +
+                                   (int64_t)sub * F::kBytes;
+                        F::store(yp, acc);  // acc now holds the stored codes as floats
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) {
+                            ssq[i] += (double)acc[i] * (double)acc[i];
+                            if constexpr (F::kScaled) cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
+                        }
+                    }
+                } else if constexpr (FINAL) {
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * s_mul[sub * VEC + i];
+                    if (live) {
+                        char *yp = reinterpret_cast<char *>(t.y) + r * t.ldy * kElem +
+                                   (int64_t)sub * F::kBytes;
+                        F::store(yp, acc);  // acc now holds the stored codes as floats
+                    }
+                    // the round's squares (and max |code|): fixed butterfly over
+                    // the row groups, then group 0 adds them to the wave's sums
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) {
-                        const double v = (double)acc[i];
-                        ssq[i] += v * v;
-                        if constexpr (F::kScaled) cmax[i] = fmaxf(cmax[i], fabsf(acc[i]));
+                        double v = (double)acc[i] * (double)acc[i];
+                        float m = fabsf(acc[i]);
+#pragma unroll
+                        for (int off = LPR; off < kWave; off <<= 1) {
+                            v += __shfl_xor(v, off);
+                            if constexpr (F::kScaled) m = fmaxf(m, __shfl_xor(m, off));
+                        }
+                        if (g == 0) {
+                            s_ssq[wave][sub * VEC + i] += v;
+                            if constexpr (F::kScaled)
+                                s_max[wave][sub * VEC + i] = fmaxf(s_max[wave][sub * VEC + i], m);
+                        }
                     }
                 } else {
+                    if (!live) continue;
                     float *sp = t.s_out + (int64_t)(rp.out_row0 + r) * t.lds + sub * VEC;
 #pragma unroll
                     for (int i = 0; i < VEC; i += 4)
@@ -529,20 +576,12 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
         }
     }
 
-    if constexpr (FINAL) {
-        // fixed-order reduction: butterfly across the row groups of a wave,
-        // then the waves in index order
-        __shared__ double s_ssq[kWaves][KT];
-        __shared__ float s_max[kWaves][KT];
+    if constexpr (FINAL && !LDS_SUMS) {
+        // the lane sums: fixed butterfly across the row groups of the wave
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             double v = ssq[i];
-            float m = 0.0f;
-            if constexpr (F::kScaled) {
-                const double c = out_scale(sub * VEC + i);
-                v *= c * c;  // exact: c is a power of two
-                m = cmax[i];
-            }
+            float m = cmax[i];
 #pragma unroll
             for (int off = LPR; off < kWave; off <<= 1) {
                 v += __shfl_xor(v, off);
@@ -553,6 +592,9 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                 s_max[wave][sub * VEC + i] = m;
             }
         }
+    }
+    if constexpr (FINAL) {
+        // the waves' sums in index order, scaled to values by c^2 (exact)
         __syncthreads();
         for (int j = tid; j < KT; j += kBlockThreads) {
             double v = s_ssq[0][j];
@@ -562,7 +604,8 @@ __global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) 
                 v += s_ssq[w][j];
                 m = fmaxf(m, s_max[w][j]);
             }
-            if (t.part_sumsq) t.part_sumsq[(int64_t)j * t.part_ld + wg] = v;
+            const double c = s_c[j];
+            if (t.part_sumsq) t.part_sumsq[(int64_t)j * t.part_ld + wg] = v * (c * c);
             if (t.part_max) t.part_max[(int64_t)j * t.part_ld + wg] = m;
         }
     }
@@ -639,19 +682,20 @@ __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, Tile t
 }
 
 // One workgroup per column: fixed-order FP64 sum of the block partials.
-__global__ __launch_bounds__(kBlockThreads) void norm_kernel(NormArgs a) {
+constexpr int kNormThreads = 1024;  // one wide workgroup per column: few, long reductions
+__global__ __launch_bounds__(kNormThreads) void norm_kernel(NormArgs a) {
     const int j = blockIdx.x;
     const double *ps = a.part_sumsq + (int64_t)j * a.part_ld;
     double v = 0.0;
     float m = 0.0f;
-    // thread t adds partials t, t + 256, t + 512, ... in that order; the loads
-    // of a group of kPer are issued before the adds
+    // thread t adds partials t, t + 1024, t + 2048, ... in that order; the
+    // loads of a group of kPer are issued before the adds
     constexpr int kPer = 16;
-    for (int base = threadIdx.x; base < a.nparts; base += kBlockThreads * kPer) {
+    for (int base = threadIdx.x; base < a.nparts; base += kNormThreads * kPer) {
         double vals[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            const int i = base + u * kBlockThreads;
+            const int i = base + u * kNormThreads;
             vals[u] = i < a.nparts ? ps[i] : 0.0;
         }
 #pragma unroll
@@ -659,23 +703,23 @@ __global__ __launch_bounds__(kBlockThreads) void norm_kernel(NormArgs a) {
     }
     if (a.part_max) {
         const float *pm = a.part_max + (int64_t)j * a.part_ld;
-        for (int base = threadIdx.x; base < a.nparts; base += kBlockThreads * kPer) {
+        for (int base = threadIdx.x; base < a.nparts; base += kNormThreads * kPer) {
             float vals[kPer];
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
-                const int i = base + u * kBlockThreads;
+                const int i = base + u * kNormThreads;
                 vals[u] = i < a.nparts ? pm[i] : 0.0f;
             }
 #pragma unroll
             for (int u = 0; u < kPer; ++u) m = fmaxf(m, vals[u]);
         }
     }
-    __shared__ double sv[kBlockThreads];
-    __shared__ float sm[kBlockThreads];
+    __shared__ double sv[kNormThreads];
+    __shared__ float sm[kNormThreads];
     sv[threadIdx.x] = v;
     sm[threadIdx.x] = m;
     __syncthreads();
-    for (int s = kBlockThreads / 2; s > 0; s >>= 1) {
+    for (int s = kNormThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             sv[threadIdx.x] += sv[threadIdx.x + s];
             sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + s]);
@@ -939,7 +983,7 @@ hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPa
 
 hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s) {
     if (k <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::norm_kernel, dim3(k), dim3(dev::kBlockThreads), 0, s, a);
+    hipLaunchKernelGGL(dev::norm_kernel, dim3(k), dim3(dev::kNormThreads), 0, s, a);
     return hipGetLastError();
 }
 

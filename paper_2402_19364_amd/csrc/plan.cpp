@@ -101,8 +101,13 @@ template int32_t choose_batch<int32_t>(int64_t, const int32_t *, const int32_t *
 template int32_t choose_batch<int64_t>(int64_t, const int64_t *, const int32_t *);
 
 // Partial slots of the final pass (one per workgroup of the level-0 pass).
+static int l0_blocks_per_wg(int dtype) {
+    return dtype == kF16 || dtype == kF8E4M3 ? kBlocksPerWgScaled : kBlocksPerWg;
+}
 static int64_t final_parts(int64_t n, int64_t rpb) { return nwg_of(n, rpb, kBlocksPerWg); }
-static int64_t final_parts(const Plan &p) { return final_parts(p.n, p.l0_rpb); }
+static int64_t final_parts(const Plan &p, int dtype) {
+    return nwg_of(p.n, p.l0_rpb, l0_blocks_per_wg(dtype));
+}
 
 arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out) {
     out = nullptr;
@@ -414,8 +419,7 @@ void plan_destroy(Plan *p) {
 }
 
 size_t op_workspace(const Plan &p, int64_t k, int dtype) {
-    (void)dtype;
-    const int64_t nb = final_parts(p);
+    const int64_t nb = final_parts(p, dtype);
     return align256((size_t)p.s_rows * k * 4) + align256((size_t)k * nb * 8) +
            align256((size_t)k * nb * 4);
 }
@@ -468,7 +472,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     if (n == 0) return ARROW_OK;
     const int kt = tile_width(k);
     const int64_t es = elem_size(op.dtype);
-    const int64_t nb = final_parts(p);
+    const int64_t nb = final_parts(p, op.dtype);
     char *w = static_cast<char *>(ws);
     float *sbuf = reinterpret_cast<float *>(w);
     w += align256((size_t)p.s_rows * k * 4);
@@ -497,7 +501,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.batch = p.up_batch;
 
     RowPass l0{};
-    set_geometry(l0, n, p.l0_rpb, kBlocksPerWg);
+    set_geometry(l0, n, p.l0_rpb, l0_blocks_per_wg(op.dtype));
     l0.ptr = p.l0_ptr;
     l0.idx = p.l0_idx;
     l0.val = p.l0_val;
@@ -558,7 +562,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
 
 int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
     const int64_t sx = elem_size(dtype);
-    const int64_t nb = final_parts(p);
+    const int64_t nb = final_parts(p, dtype);
     const bool scaled = dtype == kF16 || dtype == kF8E4M3;
     switch (kernel) {
     case ARROW_KERNEL_CHUNKS:

@@ -14,7 +14,10 @@ namespace arrow {
 constexpr int kLongRow = 32;      // rows with more entries go through the chunk pass
 constexpr int kFuseRow = 32;      // longest level-0 row after folding in rows of levels >= 1
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
-constexpr int kBlocksPerWg = 4;                    // blocks walked by one workgroup
+constexpr int kBlocksPerWg = 1;                    // blocks walked by one workgroup
+// The level-0 pass of the scaled formats (FP16, FP8) walks 4 blocks per
+// workgroup: its per-workgroup prologue (per-column output scales) is longer.
+constexpr int kBlocksPerWgScaled = 4;
 constexpr int kChunksPerBlock = 4;                // chunks per workgroup (one per wave)
 
 struct ProfRec {

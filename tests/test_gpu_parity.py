@@ -119,7 +119,8 @@ def test_strided_rows_and_hubs():
 def test_gather_batches_agree():
     # rows longer than every short batch and rows listing more than 2 partial
     # rows: each batch must give the same products (the schedule changes, the
-    # summation order does not)
+    # summation order does not); the FP64 norms sum the same squares in
+    # another fixed order, so they agree to rounding
     M = W.make_matrix("rmat", 12, "row_normalized", 51, 52, 16)
     d = A_.Decomposition.from_matrix(M, 32, seed=2)
     plan = A_.Plan(d)
@@ -138,7 +139,7 @@ def test_gather_batches_agree():
         ys, nus, _ = run_steps(plan, x, 2, torch)
         for t in range(2):
             assert torch.equal(ys[t], base[t]), (batch, t)
-            assert torch.equal(nus[t], base_nu[t]), (batch, t)
+            assert torch.allclose(nus[t], base_nu[t], rtol=1e-13, atol=0), (batch, t)
         y0 = plan_order_to_orig(ys[0].cpu().numpy().astype(np.float64), vop0)
         assert S.rel_fro(y0, ref) <= TOL
     assert plan.info()["level0_batch"] == inf["level0_batch"]
