@@ -3,19 +3,20 @@
 // Y = A X over A = sum_i P_{pi_i} B_i P_{pi_i}^T (Section 3, Eq. (1)) runs as
 // three row passes and a norm pass, all in level-0 (pi_0) order:
 //
-//   chunk pass   the head rows (rows < b, the row tiles B^(0,j) of
-//                Section 3.1) and any long row, split into nnz chunks of
-//                bounded length; each chunk writes one FP32 partial row.
-//   upper pass   the rows of levels i >= 1; their columns were mapped through
-//                pi_0 o pi_i^{-1} at plan time, so X is gathered directly in
-//                level-0 order (the forward permutation of Alg. 2 as a fused
-//                gather); partial rows of chunked rows are added; FP32 output.
-//   level-0 pass the band and head-column entries of B_0 (rows >= b, stored as
-//                16-bit codes relative to the row), plus the listed partial
-//                rows of the other passes (the reverse accumulation of Alg. 2
-//                and the Reduce of Alg. 1), scaled by the per-column factor,
-//                stored once in the storage type, with FP64 per-block column
-//                sums of squares (and max |code| for scaled formats).
+//   chunk pass   the long rows (mostly the hub rows among the head rows,
+//                the row tiles B^(0,j) of Section 3.1), split into nnz chunks
+//                of bounded length; each chunk writes one FP32 partial row.
+//   upper pass   the rows of levels i >= 1 not folded into level 0; their
+//                columns were mapped through pi_0 o pi_i^{-1} at plan time, so
+//                X is gathered directly in level-0 order (the forward
+//                permutation of Alg. 2 as a fused gather); FP32 output.
+//   level-0 pass the entries of B_0 and the folded entries of levels >= 1 of
+//                the same vertex (16-bit codes: band, head column, or far
+//                table), plus the listed partial rows of the other passes (the
+//                reverse accumulation of Alg. 2 and the Reduce of Alg. 1),
+//                scaled by the per-column factor, stored once in the storage
+//                type, with FP64 per-block column sums of squares (and max
+//                |code| for scaled formats).
 //   norm pass    fixed-order FP64 reduction of the block partials per column.
 //
 // Lane layout: every lane owns 16 bytes of an X row (VEC elements), LPR =

@@ -1,16 +1,18 @@
 // Plan construction (host) and launch orchestration.
 //
 // The decomposition's levels become three row passes in level-0 order:
-//  * chunk pass: the head rows of B_0 (rows < b: the row tiles of Section 3.1,
-//    whose entries may reach any column) and every row longer than kLongRow,
-//    cut into chunks of kChunk entries (the hub rows behind the load imbalance
-//    discussed in Section 6.2);
-//  * upper pass: each row of B_i (i >= 1) that holds entries, with columns
-//    mapped to level-0 positions through sigma_i = pi_0 o pi_i^{-1};
-//  * level-0 pass: the band and head-column entries of B_0 (rows >= b) as
-//    16-bit codes relative to the row, plus a list per row of the partial rows
-//    to add: its own chunks, then the upper-pass rows of the same vertex by
-//    level (the accumulation of Alg. 2, in a fixed order).
+//  * chunk pass: every row longer than kLongRow, cut into chunks of kChunk
+//    entries (the hub rows behind the load imbalance discussed in Section
+//    6.2; most of them are head rows of B_0, the row tiles of Section 3.1);
+//  * upper pass: the rows of B_i (i >= 1) not folded into level 0, with
+//    columns mapped to level-0 positions through sigma_i = pi_0 o pi_i^{-1};
+//  * level-0 pass: per row, the entries of B_0 and of the short rows of
+//    levels >= 1 of the same vertex (folded in), as 16-bit codes: relative to
+//    the row inside the band, the head column, or an index into the block's
+//    far-column table (folded entries and a short head row's columns beyond
+//    the band); plus a list per row of the partial rows to add: its own
+//    chunks, then the upper-pass rows of the same vertex by level (the
+//    accumulation of Alg. 2, in a fixed order).
 #include "plan.h"
 
 #include <algorithm>
@@ -169,12 +171,18 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         }
     }
 
-    // level-0 rows of the chunk pass: head rows of B_0 and long rows
+    // level-0 rows of the chunk pass: long rows (the hub rows among the head
+    // rows of B_0 in particular).  A short head row stays in the level-0
+    // pass: its columns beyond the band (q > r + b) go through the block's
+    // far-column table like folded entries.
     std::vector<uint8_t> chunked0(n, 0);
-    for (int64_t r = 0; r < n; ++r) {
-        const int64_t len = L0.row_ptr[r + 1] - L0.row_ptr[r];
-        chunked0[r] = (r < b && len > 0) || len > kLongRow;
-    }
+    auto head_far = [&](int64_t r) -> int64_t {  // entries of row r beyond the band
+        int64_t c = 0;
+        if (r < b)
+            for (int64_t e = L0.row_ptr[r]; e < L0.row_ptr[r + 1]; ++e) c += L0.col[e] > r + b;
+        return c;
+    };
+    for (int64_t r = 0; r < n; ++r) chunked0[r] = L0.row_ptr[r + 1] - L0.row_ptr[r] > kLongRow;
 
     // Level-0 block size: the largest of 256, 128, 64 rows for which 95% of
     // the blocks' entries (level 0 plus the short rows that may fold in) fit
@@ -209,6 +217,17 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     std::vector<uint8_t> fused(vrows.size(), 0);
     for (int64_t blk = 0; blk < nblocks_of(n, rpb0); ++blk) {
         int64_t far = 0;
+        // the head rows' own far entries first (a head row that does not fit
+        // the code space goes to the chunk pass)
+        for (int64_t r = blk * rpb0; r < std::min<int64_t>({n, (blk + 1) * rpb0, (int64_t)b});
+             ++r) {
+            if (chunked0[r] || !p.code16) continue;
+            const int64_t hf = head_far(r);
+            if (far + hf > far_cap)
+                chunked0[r] = 1;
+            else
+                far += hf;
+        }
         for (int64_t r = blk * rpb0; r < std::min<int64_t>(n, (blk + 1) * rpb0); ++r) {
             if (chunked0[r]) continue;
             int64_t len = L0.row_ptr[r + 1] - L0.row_ptr[r];
@@ -270,7 +289,12 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         } else {
             for (int64_t e = e0; e < e1; ++e) {
                 const int64_t q = L0.col[e];
-                if (p.code16) {
+                if (p.code16 && q > r + b) {  // a head row's column beyond the band
+                    const int64_t j = (int64_t)far_col.size() - far_ptr[blk];
+                    far_pos.push_back((uint16_t)((int64_t)l0_val.size() - l0_ptr[blk * rpb0]));
+                    l0_code.push_back((uint16_t)(3 * (int64_t)b + 1 + j));
+                    far_col.push_back((int32_t)q);
+                } else if (p.code16) {
                     const int64_t code = q >= r - b ? q - r + b : 2 * b + 1 + q;
                     l0_code.push_back((uint16_t)code);
                 } else {
