@@ -348,12 +348,39 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         up_ptr[s + 1] = (int32_t)up_val.size();
     }
     p.n_chunks = (int64_t)ch_ptr.size() - 1;
+    // Run the chunks in order of their first column, not row by row: the hub
+    // rows' chunks that cover the same stretch of columns then run together
+    // (each XCD takes a contiguous range), so their X gathers share L2.  Only
+    // the storage moves: chunk c's partial row sits at n_up + chunk_slot[c]
+    // and every list keeps its order, so the sums are unchanged.
+    std::vector<int32_t> chunk_slot(p.n_chunks);
+    {
+        std::vector<int32_t> order_c(p.n_chunks);
+        for (int64_t c = 0; c < p.n_chunks; ++c) order_c[c] = (int32_t)c;
+        std::stable_sort(order_c.begin(), order_c.end(), [&](int32_t x, int32_t y) {
+            return ch_col[ch_ptr[x]] < ch_col[ch_ptr[y]];
+        });
+        std::vector<int32_t> nptr(1, 0), ncol;
+        std::vector<float> nval;
+        ncol.reserve(ch_col.size());
+        nval.reserve(ch_val.size());
+        for (int64_t slot = 0; slot < p.n_chunks; ++slot) {
+            const int32_t c = order_c[slot];
+            chunk_slot[c] = (int32_t)slot;
+            ncol.insert(ncol.end(), ch_col.begin() + ch_ptr[c], ch_col.begin() + ch_ptr[c + 1]);
+            nval.insert(nval.end(), ch_val.begin() + ch_ptr[c], ch_val.begin() + ch_ptr[c + 1]);
+            nptr.push_back((int32_t)ncol.size());
+        }
+        ch_ptr.swap(nptr);
+        ch_col.swap(ncol);
+        ch_val.swap(nval);
+    }
     p.s_rows = p.n_up + p.n_chunks;
     for (int32_t c : ch_col) seen_ch[c] = 1;
     // partial rows listed by the upper rows: their own chunks
     for (int64_t s = 0; s < p.n_up; ++s) {
         for (int32_t c = 0; c < up_chunks[s].second; ++c)
-            up_cidx.push_back((int32_t)(p.n_up + up_chunks[s].first + c));
+            up_cidx.push_back((int32_t)(p.n_up + chunk_slot[up_chunks[s].first + c]));
         up_cptr[s + 1] = (int32_t)up_cidx.size();
     }
     // partial rows listed by the level-0 rows: own chunks, then the upper rows
@@ -361,7 +388,7 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     std::vector<int32_t> l0_cptr(n + 1, 0), l0_cidx;
     for (int64_t r = 0; r < n; ++r) {
         for (int32_t c = 0; c < l0_chunk_count[r]; ++c)
-            l0_cidx.push_back((int32_t)(p.n_up + l0_chunk_first[r] + c));
+            l0_cidx.push_back((int32_t)(p.n_up + chunk_slot[l0_chunk_first[r] + c]));
         for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si)
             if (!fused[si]) l0_cidx.push_back((int32_t)up_of[si]);
         l0_cptr[r + 1] = (int32_t)l0_cidx.size();
