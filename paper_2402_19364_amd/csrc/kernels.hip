@@ -248,8 +248,17 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 // entries of its row from LDS and issues their 8 independent X-row loads
 // before accumulating.  Entries beyond the staged range (a block with more
 // entries than fit) are read from global memory.
+// Register target: the FP32 final pass without partial-row lists and with a
+// batch of at most 5 entries fits 72 VGPRs (7 waves per SIMD) without spills
+// when the allocator is asked to; other variants keep the default.
+template <int DT, bool CONTRIB, bool FINAL, int BATCH>
+constexpr int row_waves_hint() {
+    return DT == kF32 && FINAL && !CONTRIB && BATCH != kBatchWide && BATCH <= 5 ? 7 : 1;
+}
 template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR>
-__global__ __launch_bounds__(kBlockThreads) void row_kernel(RowPass rp, Tile t) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((
+    amdgpu_waves_per_eu(row_waves_hint<DT, CONTRIB, FINAL, BATCH>()))) void row_kernel(RowPass rp,
+                                                                                         Tile t) {
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;             // lanes per row
@@ -877,9 +886,19 @@ hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const Tile &t,
                            grid, block, 0, s, rp, t);
         break;
     case kPassLevel0:
-        if (code16 && rp.fptr) {  // with folded entries of levels >= 1
+        if (code16 && rp.fptr && !rp.lists && BATCH != kBatchWide) {
+            // folded entries, no partial rows to add (every row of levels >= 1
+            // folded, no long rows): no list staging at all
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, true, false, true, OFF32, BATCH, true>), grid, block,
+                0, s, rp, t);
+        } else if (code16 && rp.fptr) {  // with folded entries of levels >= 1
             hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32, BATCH, true>),
                                grid, block, 0, s, rp, t);
+        } else if (code16 && !rp.lists && BATCH != kBatchWide) {  // one level, no long rows
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, true, false, true, OFF32, BATCH, false>), grid, block,
+                0, s, rp, t);
         } else if (code16) {
             hipLaunchKernelGGL((dev::row_kernel<KT, DT, true, true, true, OFF32, BATCH, false>),
                                grid, block, 0, s, rp, t);

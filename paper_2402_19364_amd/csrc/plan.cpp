@@ -547,6 +547,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.val = p.up_val;
     upp.cptr = p.up_cptr;
     upp.cidx = p.up_cidx;
+    upp.lists = p.up_ncontrib > 0;
     upp.b = p.b;
     upp.out_row0 = 0;
     upp.batch = p.up_batch;
@@ -558,6 +559,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     l0.val = p.l0_val;
     l0.cptr = p.l0_cptr;
     l0.cidx = p.l0_cidx;
+    l0.lists = p.l0_ncontrib > 0;
     l0.fptr = p.l0_fptr;
     l0.fcol = p.l0_fcol;
     l0.fpos = p.l0_fpos;
@@ -624,7 +626,10 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
         return p.up_nnz * 8 + (p.n_up + 1) * 8 + p.up_ncontrib * (4 + k * 4) +
                p.distinct_up * k * sx + p.n_up * k * 4;
     case ARROW_KERNEL_LEVEL0:
-        return p.l0_nnz * ((p.code16 ? 2 : 4) + 4) + (p.n + 1) * 8 +
+        // row offsets, plus list offsets unless no row lists a partial row
+        // (a short-batch pass then skips them)
+        return p.l0_nnz * ((p.code16 ? 2 : 4) + 4) +
+               (p.n + 1) * (p.l0_ncontrib > 0 || p.l0_batch == kBatchWide ? 8 : 4) +
                (p.l0_nfar > 0 ? p.l0_nfar * 6 + (nblocks_of(p.n, p.l0_rpb) + 1) * 4 : 0) +
                p.l0_ncontrib * (4 + k * 4) + p.distinct_l0 * k * sx + p.n * k * sx +
                nb * k * (8 + (scaled ? 4 : 0)) + k * (scaled ? 16 : 8);
