@@ -38,7 +38,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "plan.cpp"):
+    for f in ("kernels.hip", "kernels.h", "plan.cpp", "plan.h"):
         with open(os.path.join(ROOT, "paper_2402_19364_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
