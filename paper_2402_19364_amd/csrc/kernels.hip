@@ -752,16 +752,34 @@ __global__ __launch_bounds__(kNormThreads) void norm_kernel(NormArgs a) {
 
 // Per-column max |x| of an FP32 matrix: float bits of non-negative values
 // order like unsigned integers, so an atomic max is order independent.
+// Each workgroup reduces its rows in registers and LDS first and issues one
+// atomic per column, so the atomics stay few (one per workgroup and column).
 __global__ __launch_bounds__(kBlockThreads) void colmax_kernel(const float *x, int64_t ldx,
                                                                 int64_t n, int k,
                                                                 unsigned *out) {
+    __shared__ float s_m[kWaves][64];
     const int j = threadIdx.x % 64;
     const int rsub = threadIdx.x / 64;
-    for (int jj = j; jj < k; jj += 64) {
+    for (int jb = 0; jb < k; jb += 64) {
+        const int jj = jb + j;
         float m = 0.0f;
-        for (int64_t r = (int64_t)blockIdx.x * 4 + rsub; r < n; r += (int64_t)gridDim.x * 4)
-            m = fmaxf(m, fabsf(x[r * ldx + jj]));
-        atomicMax(out + jj, __float_as_uint(m));
+        if (jj < k) {
+            const int64_t stride = (int64_t)gridDim.x * 4;
+            int64_t r = (int64_t)blockIdx.x * 4 + rsub;
+            for (; r + 3 * stride < n; r += 4 * stride) {  // four independent loads in flight
+                const float a = x[r * ldx + jj], b = x[(r + stride) * ldx + jj];
+                const float c = x[(r + 2 * stride) * ldx + jj], d = x[(r + 3 * stride) * ldx + jj];
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(a), fabsf(b)), fmaxf(fabsf(c), fabsf(d))));
+            }
+            for (; r < n; r += stride) m = fmaxf(m, fabsf(x[r * ldx + jj]));
+        }
+        s_m[rsub][j] = m;
+        __syncthreads();
+        if (rsub == 0 && jj < k) {
+            const float mm = fmaxf(fmaxf(s_m[0][j], s_m[1][j]), fmaxf(s_m[2][j], s_m[3][j]));
+            atomicMax(out + jj, __float_as_uint(mm));
+        }
+        __syncthreads();
     }
 }
 
@@ -792,11 +810,13 @@ __global__ __launch_bounds__(kBlockThreads) void permute_in_kernel(
     constexpr int RPB = kBlockThreads / LPR;
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     const int sub = threadIdx.x % LPR;
-    const int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
     float m[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i) m[i] = 0.0f;
-    if (p < n) {
+    // rows in a grid-stride loop: the running max |code| per column stays in
+    // registers and each workgroup issues one atomic per column at the end
+    for (int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR; p < n;
+         p += (int64_t)gridDim.x * RPB) {
         const float *src = x + (int64_t)vop[p] * ldx + sub * VEC;
         float v[VEC];
 #pragma unroll
@@ -810,15 +830,24 @@ __global__ __launch_bounds__(kBlockThreads) void permute_in_kernel(
         }
         F::store(reinterpret_cast<char *>(xp) + (p * ld * kElem) + sub * F::kBytes, v);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) m[i] = fabsf(v[i]);
+        for (int i = 0; i < VEC; ++i) m[i] = fmaxf(m[i], fabsf(v[i]));
     }
     if (codemax) {
+        __shared__ float s_m[kWaves][KT];
+        const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             float mm = m[i];
 #pragma unroll
             for (int off = LPR; off < kWave; off <<= 1) mm = fmaxf(mm, __shfl_xor(mm, off));
-            if ((threadIdx.x % kWave) < LPR) atomicMax(codemax + sub * VEC + i, __float_as_uint(mm));
+            if (lane < LPR) s_m[wave][sub * VEC + i] = mm;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < KT; j += kBlockThreads) {
+            float mm = s_m[0][j];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_m[w][j]);
+            atomicMax(codemax + j, __float_as_uint(mm));
         }
     }
 }
@@ -967,7 +996,9 @@ hipError_t launch_perm_in_t(const float *x, int64_t ldx, const int32_t *vop, int
                             int64_t ld, const float *scale, unsigned *codemax, hipStream_t s) {
     constexpr int LPR = KT / dev::Fmt<DT>::kVec;
     constexpr int RPB = dev::kBlockThreads / LPR;
-    dim3 grid((unsigned)((n + RPB - 1) / RPB));
+    int64_t blocks = (n + RPB - 1) / RPB;
+    if (blocks > 4096) blocks = 4096;  // grid-stride: few atomics per column
+    dim3 grid((unsigned)blocks);
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL((dev::permute_in_kernel<KT, DT>), grid, dim3(dev::kBlockThreads), 0, s, x,
                        ldx, vop, n, xp, ld, scale, codemax);
@@ -1018,7 +1049,7 @@ hipError_t launch_colmax(const float *x, int64_t ldx, int64_t n, int k, unsigned
                          hipStream_t s) {
     if (n <= 0 || k <= 0) return hipSuccess;
     int64_t blocks = (n + 4 * 64 - 1) / (4 * 64);
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(dev::colmax_kernel, dim3((unsigned)blocks), dim3(dev::kBlockThreads), 0, s,
                        x, ldx, n, k, out);
     return hipGetLastError();
