@@ -136,8 +136,11 @@ void arrow_decomp_destroy(arrow_decomp_t d);
 /*
  * Upload a decomposition to GPU `device` as a plan (the arrow tiles of
  * Section 3.1 become row blocks of work; the level maps pi_i become
- * precomputed gather indices into the level-0 order).  Synchronous: returns
- * after the upload finished.  The plan does not reference `d` afterwards.
+ * precomputed gather indices into the level-0 order).  Short rows of levels
+ * >= 1 are folded into the level-0 row of their vertex (the products of
+ * Alg. 2 reassociated per vertex); long rows of any level become chunks with
+ * FP32 partial rows.  Synchronous: returns after the upload finished.  The
+ * plan does not reference `d` afterwards.
  */
 arrow_status_t arrow_plan_create(arrow_decomp_t d, int32_t device, void *stream,
                                  arrow_plan_t *out);
@@ -147,10 +150,10 @@ typedef struct {
     int64_t n, nnz;
     int32_t b, levels;
     int64_t footprint_bytes;  /* device memory owned by the plan */
-    int64_t chunked_rows;     /* rows split into nnz chunks (the head rows and long rows) */
+    int64_t chunked_rows;     /* rows split into nnz chunks (rows of more than 32 entries) */
     int64_t chunks;           /* number of chunks */
     int64_t upper_rows;       /* rows of levels >= 1 computed by the upper pass */
-    int64_t contributions;    /* summands gathered by the level-0 pass */
+    int64_t contributions;    /* partial rows (chunks, upper rows) listed by level-0 rows */
     double a_inf_norm;        /* max_i sum_j |A_ij| (bounds the FP8/FP16 scales) */
     int32_t upper_batch;      /* gather batch of the upper / level-0 passes: 0 = wide, */
     int32_t level0_batch;     /* else entries gathered per row and batch (4..8) */
@@ -180,7 +183,7 @@ arrow_status_t arrow_plan_set_batch(arrow_plan_t p, int32_t kernel, int32_t batc
 
 /* Kernel ids for arrow_plan_kernel_bytes and the profiling counters. */
 enum {
-    ARROW_KERNEL_CHUNKS = 0,  /* head rows and long rows, nnz-balanced chunks */
+    ARROW_KERNEL_CHUNKS = 0,  /* long rows (hub rows), nnz-balanced chunks */
     ARROW_KERNEL_UPPER = 1,   /* rows of levels >= 1 (gathered through pi_0 o pi_i^{-1}) */
     ARROW_KERNEL_LEVEL0 = 2,  /* level-0 band + head columns + cross-level sum + store */
     ARROW_KERNEL_NORM = 3,    /* FP64 column norms and next scales */

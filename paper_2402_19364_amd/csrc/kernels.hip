@@ -270,6 +270,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     using IdxT = typename std::conditional<CODE16, uint16_t, int32_t>::type;
 
     __shared__ int32_t s_ptr[kMaxBlockRows + 1];
+    __shared__ uint8_t s_ord[kMaxBlockRows];  // processing order of the block's rows
     __shared__ int32_t s_cptr[CONTRIB ? kMaxBlockRows + 1 : 1];
     __shared__ int32_t s_cidx[CONTRIB ? kStageLists : 1];
     __shared__ IdxT s_idx[kStageEntries];
@@ -350,6 +351,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
         for (int i = tid; i <= nr; i += kBlockThreads) {
             s_ptr[i] = rp.ptr[row0 + i];
             if constexpr (CONTRIB) s_cptr[i] = rp.cptr[row0 + i];
+            if (rp.order && i < nr) s_ord[i] = rp.order[row0 + i];
         }
         if constexpr (FAR) {
             if (tid < 2) s_fb[tid] = rp.fptr[row0 / rp.rows_per_block + tid];
@@ -395,9 +397,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
             // wave-uniform trip count: the final pass reduces across the
             // wave's row groups every round (rows past the block end are idle)
             for (int rbase = wave * RPW; rbase < nr; rbase += RPR) {
-                const int rl = rbase + g;
-                const bool live = rl < nr;
-                const int rs = live ? rl : nr - 1;  // an idle group reads a valid row...
+                const int rq = rbase + g;  // slot in the block's processing order
+                const bool live = rq < nr;
+                // the row of this slot (the plan may order a block's rows by
+                // length, so a wave's row groups get rows of similar length)
+                const int rl = live ? (rp.order ? (int)s_ord[rq] : rq) : nr - 1;
+                const int rs = rl;  // an idle group reads a valid row...
                 const int64_t r = row0 + rl;
                 const int a = s_ptr[rs] - e0;
                 const int len = live ? s_ptr[rs + 1] - e0 - a : 0;  // ...and gathers nothing

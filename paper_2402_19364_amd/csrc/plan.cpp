@@ -396,6 +396,31 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     p.l0_batch = p.l0_batch_auto = choose_batch<int32_t>(n, l0_ptr.data(), l0_cptr.data());
     p.up_batch = p.up_batch_auto =
         choose_batch<int32_t>(p.n_up, up_ptr.data(), up_cptr.data());
+    // Passes of mixed row lengths (wide batch): process each block's rows
+    // longest first, so the row groups of a wave get rows of similar length
+    // (a wave waits for its longest row).  Only the schedule changes.
+    auto block_order = [&](int64_t rows, int64_t rpb, const std::vector<int32_t> &ptr,
+                           const std::vector<int32_t> &cptr) {
+        std::vector<uint8_t> ord(rows);
+        std::vector<int32_t> idx;
+        for (int64_t r0 = 0; r0 < rows; r0 += rpb) {
+            const int64_t nr = std::min<int64_t>(rpb, rows - r0);
+            idx.resize(nr);
+            for (int64_t i = 0; i < nr; ++i) idx[i] = (int32_t)i;
+            auto work = [&](int32_t i) {
+                const int64_t r = r0 + i;
+                return (int64_t)(ptr[r + 1] - ptr[r]) + 2 * (int64_t)(cptr[r + 1] - cptr[r]);
+            };
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int32_t x, int32_t y) { return work(x) > work(y); });
+            for (int64_t i = 0; i < nr; ++i) ord[r0 + i] = (uint8_t)idx[i];
+        }
+        return ord;
+    };
+    std::vector<uint8_t> l0_order, up_order;
+    if (p.l0_batch_auto == kBatchWide) l0_order = block_order(n, rpb0, l0_ptr, l0_cptr);
+    if (p.up_batch_auto == kBatchWide && p.n_up > 0)
+        up_order = block_order(p.n_up, kRowsPerBlock, up_ptr, up_cptr);
     p.l0_nnz = (int64_t)l0_val.size();
     p.l0_ncontrib = (int64_t)l0_cidx.size();
     p.up_nnz = (int64_t)up_val.size();
@@ -427,6 +452,8 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     UP(p.l0_val, l0_val);
     UP(p.l0_cptr, l0_cptr);
     UP(p.l0_cidx, l0_cidx);
+    UP(p.l0_order, l0_order);
+    UP(p.up_order, up_order);
     if (p.l0_nfar > 0) {
         UP(p.l0_fptr, far_ptr);
         UP(p.l0_fcol, far_col);
@@ -548,6 +575,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.cptr = p.up_cptr;
     upp.cidx = p.up_cidx;
     upp.lists = p.up_ncontrib > 0;
+    upp.order = p.up_order;
     upp.b = p.b;
     upp.out_row0 = 0;
     upp.batch = p.up_batch;
@@ -560,6 +588,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     l0.cptr = p.l0_cptr;
     l0.cidx = p.l0_cidx;
     l0.lists = p.l0_ncontrib > 0;
+    l0.order = p.l0_order;
     l0.fptr = p.l0_fptr;
     l0.fcol = p.l0_fcol;
     l0.fpos = p.l0_fpos;
@@ -623,13 +652,15 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
         return p.ch_nnz * 8 + (p.n_chunks + 1) * 4 + p.distinct_ch * k * sx + p.n_chunks * k * 4;
     case ARROW_KERNEL_UPPER:
         if (p.n_up == 0) return 0;
-        return p.up_nnz * 8 + (p.n_up + 1) * 8 + p.up_ncontrib * (4 + k * 4) +
+        return p.up_nnz * 8 + (p.n_up + 1) * 8 + (p.up_order ? p.n_up : 0) +
+               p.up_ncontrib * (4 + k * 4) +
                p.distinct_up * k * sx + p.n_up * k * 4;
     case ARROW_KERNEL_LEVEL0:
         // row offsets, plus list offsets unless no row lists a partial row
         // (a short-batch pass then skips them)
         return p.l0_nnz * ((p.code16 ? 2 : 4) + 4) +
                (p.n + 1) * (p.l0_ncontrib > 0 || p.l0_batch == kBatchWide ? 8 : 4) +
+               (p.l0_order ? p.n : 0) +
                (p.l0_nfar > 0 ? p.l0_nfar * 6 + (nblocks_of(p.n, p.l0_rpb) + 1) * 4 : 0) +
                p.l0_ncontrib * (4 + k * 4) + p.distinct_l0 * k * sx + p.n * k * sx +
                nb * k * (8 + (scaled ? 4 : 0)) + k * (scaled ? 16 : 8);

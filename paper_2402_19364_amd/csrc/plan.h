@@ -12,7 +12,7 @@
 namespace arrow {
 
 constexpr int kLongRow = 32;      // rows with more entries go through the chunk pass
-constexpr int kFuseRow = 32;      // longest level-0 row after folding in rows of levels >= 1
+constexpr int kFuseRow = 64;      // longest level-0 row after folding in rows of levels >= 1
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
 constexpr int kBlocksPerWg = 1;                    // blocks walked by one workgroup
 // The level-0 pass of the scaled formats (FP16, FP8) walks 4 blocks per
@@ -38,6 +38,7 @@ struct Plan {
     void *l0_idx = nullptr;
     float *l0_val = nullptr;
     int32_t *l0_cptr = nullptr;
+    uint8_t *l0_order = nullptr;        // per-block processing order (wide batch), or null
     int32_t *l0_cidx = nullptr;
     int64_t l0_nnz = 0, l0_ncontrib = 0;
     int32_t l0_rpb = kMaxBlockRows;     // rows per staged block of the level-0 pass
@@ -51,6 +52,7 @@ struct Plan {
     int32_t *up_ptr = nullptr, *up_col = nullptr;
     float *up_val = nullptr;
     int32_t *up_cptr = nullptr, *up_cidx = nullptr;
+    uint8_t *up_order = nullptr;
     int64_t up_nnz = 0, up_ncontrib = 0;
     // chunk pass
     int64_t n_chunks = 0, chunked_rows = 0;
