@@ -216,16 +216,19 @@ def main():
         a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         a.fill_(1)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.fill_(0)
+        arrow.copy(a, b, nbytes)  # untimed first launch
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.copy_calib + 1)]
         torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(args.copy_calib):
+        evs[0].record()
+        for i in range(args.copy_calib):
             arrow.copy(a, b, nbytes)
-        ev1.record()
+            evs[i + 1].record()
         torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.copy_calib
+        ms = float(np.median([evs[i].elapsed_time(evs[i + 1]) for i in range(args.copy_calib)]))
         print(json.dumps({"copy_bytes": nbytes, "launches": args.copy_calib,
-                          "ms_per_copy": ms, "GBps": 2 * nbytes / ms / 1e6}), flush=True)
+                          "ms_per_copy_p50": round(ms, 4),
+                          "GBps": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
         return
 
     w = W.WORKLOADS[args.workload]

@@ -1002,7 +1002,7 @@ hipError_t launch_perm_in_t(const float *x, int64_t ldx, const int32_t *vop, int
     constexpr int LPR = KT / dev::Fmt<DT>::kVec;
     constexpr int RPB = dev::kBlockThreads / LPR;
     int64_t blocks = (n + RPB - 1) / RPB;
-    if (blocks > 4096) blocks = 4096;  // grid-stride: few atomics per column
+    if (codemax && blocks > 4096) blocks = 4096;  // grid-stride: few atomics per column
     dim3 grid((unsigned)blocks);
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL((dev::permute_in_kernel<KT, DT>), grid, dim3(dev::kBlockThreads), 0, s, x,
