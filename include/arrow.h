@@ -35,9 +35,11 @@
  *     Row and column storage must be 16-byte aligned: the base pointer and
  *     ld * element_size must be multiples of 16.
  *   - Feature width k must be a positive multiple of 16.
- *   - Decompositions and plans are immutable after creation; concurrent calls
- *     on one plan from several streams are safe when each call has its own
- *     workspace and outputs.
+ *   - Decompositions and plans are immutable after creation, apart from the
+ *     schedule settings arrow_plan_set_batch and arrow_profile_enable (call
+ *     those while no other host thread uses the plan); concurrent calls on one
+ *     plan from several streams are safe when each call has its own workspace
+ *     and outputs.
  */
 #ifndef ARROW_H
 #define ARROW_H
