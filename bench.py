@@ -8,8 +8,9 @@ renormalisation folded into the next product, permute the result back.  The
 decomposition (host) and the plan upload happen once, before timing.
 
 Prints one JSON line: whole-step algorithmic GB/s (value), its fraction of the
-8 TB/s HBM peak, per-iteration p50/p99 latency, the plain CSR SpMM baseline on
-the same GPU (as-generated order, same dtype/k/norm epilogue), the roofline of
+8 TB/s HBM peak, per-iteration p50/p99 latency, the plain CSR SpMM baselines on
+the same GPU (hand-written and rocSPARSE; FP32, as-generated order, same k and
+norm epilogue), the roofline of
 the dominant kernel (level-0 pass; its duration measured with HIP events around
 every launch on the launch stream) and the FP64 oracle timed on host cores.
 """
