@@ -89,7 +89,11 @@ def serving_bench(args):
     """Poisson stream of iterated-SpMM jobs over a pool of graphs (3D grids
     32^3..128^3, R-MAT 2^16..2^20 with degree 8..32), k in {16,32,64,128},
     FP32/BF16, T in 5..50, X_0 drawn on the device from a per-request seed.
-    Capacity is measured closed-loop; latency is reported at 0.8x capacity."""
+    Capacity is measured closed-loop (all requests at t = 0); the same request
+    mix then arrives as a Poisson stream at fractions of that capacity, and the
+    line's value is the p99 latency at 0.8x.  The closed loop batches every
+    request it can, so a Poisson stream, which batches less, may saturate
+    below 1.0x."""
     import torch
 
     import paper_2402_19364_amd as arrow
@@ -142,7 +146,8 @@ def serving_bench(args):
     log(f"[serving] closed loop: {len(closed)} requests in {makespan:.2f}s -> {mu:.1f} req/s")
     results = {}
     for frac in args.serving_load:
-        reqs = make(args.serving_requests, 2 + int(frac * 100))
+        # the closed loop's request mix, with Poisson arrivals at frac x capacity
+        reqs = make(args.serving_requests, 1)
         t = 0.0
         for r in reqs:
             t += rng.exponential(1.0 / (frac * mu))
@@ -159,7 +164,8 @@ def serving_bench(args):
         log(f"[serving] load {frac:g}: {results[f'{frac:g}']}")
     line = {
         "metric": "serving latency of iterated arrow-SpMM jobs (continuous batching)",
-        "value": results[f"{args.serving_load[0]:g}"]["p99_ms"], "unit": "ms (p99)",
+        "value": results["0.8" if "0.8" in results else f"{args.serving_load[0]:g}"]["p99_ms"],
+        "unit": "ms (p99)", "value_load": 0.8 if "0.8" in results else args.serving_load[0],
         "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
         "config": {"workload": "serving", "pool": {k: {"n": v[0], "nnz": v[1]}
                                                     for k, v in sizes.items()},
@@ -190,7 +196,7 @@ def main():
                     help="only run the streaming copy kernel N times over 1 GiB")
     ap.add_argument("--serving", action="store_true", help="run the serving benchmark")
     ap.add_argument("--serving-requests", type=int, default=300)
-    ap.add_argument("--serving-load", type=float, nargs="+", default=[0.8, 0.5, 0.95])
+    ap.add_argument("--serving-load", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     args = ap.parse_args()
 

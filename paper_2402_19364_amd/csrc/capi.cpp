@@ -395,7 +395,7 @@ arrow_status_t arrow_permute_out(arrow_plan_t p, const void *y_plan, int64_t ld,
     const int64_t es = arrow::elem_size(dtype);
     for (int64_t c0 = 0; c0 < k; c0 += kt) {
         hipError_t e = arrow::launch_permute_out(
-            kt, dtype, static_cast<const char *>(y_plan) + c0 * es, ld, P.pos0, P.n,
+            kt, dtype, static_cast<const char *>(y_plan) + c0 * es, ld, P.vop0, P.n,
             x_scale ? x_scale + c0 : nullptr, col_factor ? col_factor + c0 : nullptr, y + c0, ldy,
             s);
         if (e != hipSuccess) {

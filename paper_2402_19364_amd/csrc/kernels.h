@@ -90,7 +90,7 @@ hipError_t launch_scale_from_max(int dtype, unsigned *bits, float *scale, int k,
 hipError_t launch_permute_in(int kt, int dtype, const float *x, int64_t ldx, const int32_t *vop,
                              int64_t n, void *xp, int64_t ld, const float *scale,
                              unsigned *codemax, hipStream_t s);
-hipError_t launch_permute_out(int kt, int dtype, const void *yp, int64_t ld, const int32_t *pos0,
+hipError_t launch_permute_out(int kt, int dtype, const void *yp, int64_t ld, const int32_t *vop,
                               int64_t n, const float *scale, const double *factor, float *y,
                               int64_t ldy, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);

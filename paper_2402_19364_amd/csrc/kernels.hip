@@ -857,12 +857,10 @@ __global__ __launch_bounds__(kBlockThreads) void permute_in_kernel(
     }
 }
 
-// y[v] = yp[pos0[v]] * scale * factor (FP32 out).
+// y[vop[p]] = yp[p] * scale * factor (FP32 out).
 template <int KT, int DT>
-// Gather form: a lane group takes original row v and reads plan row pos0[v],
-// so the FP32 output is written in coalesced row order.
 __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
-    const void *yp, int64_t ld, const int32_t *pos0, int64_t n, const float *scale,
+    const void *yp, int64_t ld, const int32_t *vop, int64_t n, const float *scale,
     const double *factor, float *y, int64_t ldy) {
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
@@ -870,9 +868,8 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
     constexpr int RPB = kBlockThreads / LPR;
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     const int sub = threadIdx.x % LPR;
-    const int64_t v_row = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
-    if (v_row >= n) return;
-    const int64_t p = pos0[v_row];
+    const int64_t p = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+    if (p >= n) return;
     float v[VEC];
     F::decode(*reinterpret_cast<const typename F::Raw *>(reinterpret_cast<const char *>(yp) +
                                                           p * ld * kElem + sub * F::kBytes),
@@ -885,7 +882,7 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
         if (factor) f *= factor[j];
         v[i] = (float)((double)v[i] * f);
     }
-    float *dst = y + v_row * ldy + sub * VEC;
+    float *dst = y + (int64_t)vop[p] * ldy + sub * VEC;
 #pragma unroll
     for (int i = 0; i < VEC; i += 4)
         *reinterpret_cast<float4 *>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
@@ -1014,7 +1011,7 @@ hipError_t launch_perm_in_t(const float *x, int64_t ldx, const int32_t *vop, int
 }
 
 template <int KT, int DT>
-hipError_t launch_perm_out_t(const void *yp, int64_t ld, const int32_t *pos0, int64_t n,
+hipError_t launch_perm_out_t(const void *yp, int64_t ld, const int32_t *vop, int64_t n,
                              const float *scale, const double *factor, float *y, int64_t ldy,
                              hipStream_t s) {
     constexpr int LPR = KT / dev::Fmt<DT>::kVec;
@@ -1022,7 +1019,7 @@ hipError_t launch_perm_out_t(const void *yp, int64_t ld, const int32_t *pos0, in
     dim3 grid((unsigned)((n + RPB - 1) / RPB));
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL((dev::permute_out_kernel<KT, DT>), grid, dim3(dev::kBlockThreads), 0, s,
-                       yp, ld, pos0, n, scale, factor, y, ldy);
+                       yp, ld, vop, n, scale, factor, y, ldy);
     return hipGetLastError();
 }
 
@@ -1086,11 +1083,11 @@ hipError_t launch_permute_in(int kt, int dtype, const float *x, int64_t ldx, con
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_permute_out(int kt, int dtype, const void *yp, int64_t ld, const int32_t *pos0,
+hipError_t launch_permute_out(int kt, int dtype, const void *yp, int64_t ld, const int32_t *vop,
                               int64_t n, const float *scale, const double *factor, float *y,
                               int64_t ldy, hipStream_t s) {
 #define ARROW_POUT(KT_, DT_) \
-    if (kt == KT_ && dtype == DT_) return launch_perm_out_t<KT_, DT_>(yp, ld, pos0, n, scale, factor, y, ldy, s);
+    if (kt == KT_ && dtype == DT_) return launch_perm_out_t<KT_, DT_>(yp, ld, vop, n, scale, factor, y, ldy, s);
 #define ARROW_POUT_DT(DT_) ARROW_POUT(16, DT_) ARROW_POUT(32, DT_) ARROW_POUT(64, DT_) ARROW_POUT(128, DT_)
     ARROW_POUT_DT(kF32) ARROW_POUT_DT(kF16) ARROW_POUT_DT(kBF16) ARROW_POUT_DT(kF8E4M3)
 #undef ARROW_POUT_DT

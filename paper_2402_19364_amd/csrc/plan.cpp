@@ -468,7 +468,6 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     UP(p.ch_col, ch_col);
     UP(p.ch_val, ch_val);
     UP(p.vop0, L0.vop);
-    UP(p.pos0, pos0);
 #undef UP
     if (st == ARROW_OK) {
         e = hipStreamSynchronize(stream);

@@ -59,9 +59,8 @@ struct Plan {
     int32_t *ch_ptr = nullptr, *ch_col = nullptr;
     float *ch_val = nullptr;
     int64_t ch_nnz = 0;
-    // permutation pi_0^{-1} (vertex of each position) and pi_0 (position of each vertex)
+    // permutation pi_0^{-1}
     int32_t *vop0 = nullptr;
-    int32_t *pos0 = nullptr;
 
     // gather batch of the upper and level-0 passes (kBatchWide or a short batch)
     int32_t up_batch = kBatchWide, l0_batch = kBatchWide;
