@@ -37,7 +37,11 @@ struct RowPass {
     const int32_t *cidx;  // rows of the partial buffer
     int32_t lists;        // 0: no row lists a partial row (cptr is all zero)
     const uint8_t *order; // per row: the row within its block processed at this
-                          // slot (rows of a block ordered by length), or null
+                          // slot (rows of a block ordered by length), or null;
+                          // followed by wide batches only
+    const int32_t *blk_e; // [blocks + 1] entry offset of each block (ptr at the
+                          // block starts), or null
+    const int32_t *blk_c; // [blocks + 1] list offset of each block (with blk_e)
     // level-0 pass with 16-bit codes: code 3b+1+j names entry j of the block's
     // far-column table fcol[fptr[block] ...]; fpos gives the entry's index
     // within the block, so a staged block scatters the table next to its

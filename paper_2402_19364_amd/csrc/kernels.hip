@@ -270,7 +270,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     using IdxT = typename std::conditional<CODE16, uint16_t, int32_t>::type;
 
     __shared__ int32_t s_ptr[kMaxBlockRows + 1];
-    __shared__ uint8_t s_ord[kMaxBlockRows];  // processing order of the block's rows
+    // processing order of the block's rows (wide batches only: short batches
+    // serve passes of uniform rows and keep their LDS for occupancy)
+    constexpr bool ORDER = BATCH == kBatchWide;
+    __shared__ uint8_t s_ord[ORDER ? kMaxBlockRows : 1];
+    const bool ordered = ORDER && rp.order != nullptr;
     __shared__ int32_t s_cptr[CONTRIB ? kMaxBlockRows + 1 : 1];
     __shared__ int32_t s_cidx[CONTRIB ? kStageLists : 1];
     __shared__ IdxT s_idx[kStageEntries];
@@ -347,42 +351,66 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
         if (row0 >= rp.nrows) break;
         const int nr = (int)(row0 + rp.rows_per_block < rp.nrows ? rp.rows_per_block
                                                                   : rp.nrows - row0);
+        const int blk = (int)(row0 / rp.rows_per_block);
+        // The block's entry, list and far-table ranges: from the plan's
+        // per-block offset tables when present (small, L2-resident), so the
+        // entries are staged together with the row offsets in one round trip;
+        // otherwise from the staged row offsets, one round trip later.
+        const bool one_phase = rp.blk_e != nullptr;
+        int e0 = 0, ne = 0, cb = 0, nc = 0, fb = 0, nf = 0;
+        if (one_phase) {
+            e0 = rp.blk_e[blk];
+            ne = rp.blk_e[blk + 1] - e0;
+            if constexpr (CONTRIB) {
+                cb = rp.blk_c[blk];
+                nc = rp.blk_c[blk + 1] - cb;
+            }
+            if constexpr (FAR) {
+                fb = rp.fptr[blk];
+                nf = rp.fptr[blk + 1] - fb;
+            }
+        }
         __syncthreads();  // the previous block is done with the staged data
         for (int i = tid; i <= nr; i += kBlockThreads) {
             s_ptr[i] = rp.ptr[row0 + i];
             if constexpr (CONTRIB) s_cptr[i] = rp.cptr[row0 + i];
-            if (rp.order && i < nr) s_ord[i] = rp.order[row0 + i];
+            if (ordered && i < nr) s_ord[i] = rp.order[row0 + i];
         }
-        if constexpr (FAR) {
-            if (tid < 2) s_fb[tid] = rp.fptr[row0 / rp.rows_per_block + tid];
+        if (!one_phase) {
+            if constexpr (FAR) {
+                if (tid < 2) s_fb[tid] = rp.fptr[blk + tid];
+            }
+            __syncthreads();
+            // block-uniform values: kept in scalar registers
+            e0 = __builtin_amdgcn_readfirstlane(s_ptr[0]);
+            ne = __builtin_amdgcn_readfirstlane(s_ptr[nr]) - e0;
+            if constexpr (CONTRIB) {
+                cb = __builtin_amdgcn_readfirstlane(s_cptr[0]);
+                nc = __builtin_amdgcn_readfirstlane(s_cptr[nr]) - cb;
+            }
+            if constexpr (FAR) {
+                fb = __builtin_amdgcn_readfirstlane(s_fb[0]);
+                nf = __builtin_amdgcn_readfirstlane(s_fb[1]) - fb;
+            }
         }
-        __syncthreads();
-        const int e0 = s_ptr[0];
-        const int ne = s_ptr[nr] - e0;
         // Block-uniform choice: the block's entries come from LDS when they fit,
         // otherwise every entry is read from global memory.
         const bool staged = ne <= kStageEntries;
-        int fb = 0;
-        if constexpr (FAR) fb = s_fb[0];
         if (staged) {
             for (int i = tid; i < ne; i += kBlockThreads) {
                 s_idx[i] = gidx[e0 + i];
                 s_val[i] = rp.val[e0 + i];
             }
             if constexpr (FAR) {
-                const int nf = s_fb[1] - fb;  // <= ne, every fpos < ne
-                for (int i = tid; i < nf; i += kBlockThreads) {
+                for (int i = tid; i < nf; i += kBlockThreads) {  // nf <= ne, every fpos < ne
                     const int pos = rp.fpos[fb + i];
                     s_fcol[pos < kStageEntries ? pos : kStageEntries - 1] = rp.fcol[fb + i];
                 }
             }
         }
         // the block's list of partial rows, staged the same way
-        int cb = 0;
         bool cstaged = true;
         if constexpr (CONTRIB) {
-            cb = s_cptr[0];
-            const int nc = s_cptr[nr] - cb;
             cstaged = nc <= kStageLists;
             if (cstaged)
                 for (int i = tid; i < nc; i += kBlockThreads) s_cidx[i] = rp.cidx[cb + i];
@@ -401,7 +429,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
                 const bool live = rq < nr;
                 // the row of this slot (the plan may order a block's rows by
                 // length, so a wave's row groups get rows of similar length)
-                const int rl = live ? (rp.order ? (int)s_ord[rq] : rq) : nr - 1;
+                const int rl = live ? (ordered ? (int)s_ord[rq] : rq) : nr - 1;
                 const int rs = rl;  // an idle group reads a valid row...
                 const int64_t r = row0 + rl;
                 const int a = s_ptr[rs] - e0;

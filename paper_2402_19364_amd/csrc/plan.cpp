@@ -417,6 +417,20 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         }
         return ord;
     };
+    // per-block entry / list offsets (the row offsets at the block starts)
+    auto block_offsets = [&](int64_t rows, int64_t rpb, const std::vector<int32_t> &ptr) {
+        std::vector<int32_t> o;
+        for (int64_t r0 = 0; r0 < rows; r0 += rpb) o.push_back(ptr[r0]);
+        o.push_back(ptr[rows]);
+        return o;
+    };
+    std::vector<int32_t> l0_blk_e = block_offsets(n, rpb0, l0_ptr);
+    std::vector<int32_t> l0_blk_c = block_offsets(n, rpb0, l0_cptr);
+    std::vector<int32_t> up_blk_e, up_blk_c;
+    if (p.n_up > 0) {
+        up_blk_e = block_offsets(p.n_up, kRowsPerBlock, up_ptr);
+        up_blk_c = block_offsets(p.n_up, kRowsPerBlock, up_cptr);
+    }
     std::vector<uint8_t> l0_order, up_order;
     if (p.l0_batch_auto == kBatchWide) l0_order = block_order(n, rpb0, l0_ptr, l0_cptr);
     if (p.up_batch_auto == kBatchWide && p.n_up > 0)
@@ -454,6 +468,10 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     UP(p.l0_cidx, l0_cidx);
     UP(p.l0_order, l0_order);
     UP(p.up_order, up_order);
+    UP(p.l0_blk_e, l0_blk_e);
+    UP(p.l0_blk_c, l0_blk_c);
+    UP(p.up_blk_e, up_blk_e);
+    UP(p.up_blk_c, up_blk_c);
     if (p.l0_nfar > 0) {
         UP(p.l0_fptr, far_ptr);
         UP(p.l0_fcol, far_col);
@@ -576,6 +594,8 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.cidx = p.up_cidx;
     upp.lists = p.up_ncontrib > 0;
     upp.order = p.up_order;
+    upp.blk_e = p.up_batch != kBatchWide ? p.up_blk_e : nullptr;
+    upp.blk_c = p.up_batch != kBatchWide ? p.up_blk_c : nullptr;
     upp.b = p.b;
     upp.out_row0 = 0;
     upp.batch = p.up_batch;
@@ -589,6 +609,10 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     l0.cidx = p.l0_cidx;
     l0.lists = p.l0_ncontrib > 0;
     l0.order = p.l0_order;
+    // one-round-trip staging for the short batches (measured: a little faster
+    // on the grids, a little slower on the wide R-MAT pass)
+    l0.blk_e = p.l0_batch != kBatchWide ? p.l0_blk_e : nullptr;
+    l0.blk_c = p.l0_batch != kBatchWide ? p.l0_blk_c : nullptr;
     l0.fptr = p.l0_fptr;
     l0.fcol = p.l0_fcol;
     l0.fpos = p.l0_fpos;
@@ -653,6 +677,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
     case ARROW_KERNEL_UPPER:
         if (p.n_up == 0) return 0;
         return p.up_nnz * 8 + (p.n_up + 1) * 8 + (p.up_order ? p.n_up : 0) +
+               (p.up_batch != kBatchWide ? (nblocks_of(p.n_up, kRowsPerBlock) + 1) * 8 : 0) +
                p.up_ncontrib * (4 + k * 4) +
                p.distinct_up * k * sx + p.n_up * k * 4;
     case ARROW_KERNEL_LEVEL0:
@@ -661,6 +686,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
         return p.l0_nnz * ((p.code16 ? 2 : 4) + 4) +
                (p.n + 1) * (p.l0_ncontrib > 0 || p.l0_batch == kBatchWide ? 8 : 4) +
                (p.l0_order ? p.n : 0) +
+               (p.l0_batch != kBatchWide ? (nblocks_of(p.n, p.l0_rpb) + 1) * 8 : 0) +
                (p.l0_nfar > 0 ? p.l0_nfar * 6 + (nblocks_of(p.n, p.l0_rpb) + 1) * 4 : 0) +
                p.l0_ncontrib * (4 + k * 4) + p.distinct_l0 * k * sx + p.n * k * sx +
                nb * k * (8 + (scaled ? 4 : 0)) + k * (scaled ? 16 : 8);

@@ -39,6 +39,7 @@ struct Plan {
     float *l0_val = nullptr;
     int32_t *l0_cptr = nullptr;
     uint8_t *l0_order = nullptr;        // per-block processing order (wide batch), or null
+    int32_t *l0_blk_e = nullptr, *l0_blk_c = nullptr;  // per-block entry / list offsets
     int32_t *l0_cidx = nullptr;
     int64_t l0_nnz = 0, l0_ncontrib = 0;
     int32_t l0_rpb = kMaxBlockRows;     // rows per staged block of the level-0 pass
@@ -53,6 +54,7 @@ struct Plan {
     float *up_val = nullptr;
     int32_t *up_cptr = nullptr, *up_cidx = nullptr;
     uint8_t *up_order = nullptr;
+    int32_t *up_blk_e = nullptr, *up_blk_c = nullptr;
     int64_t up_nnz = 0, up_ncontrib = 0;
     // chunk pass
     int64_t n_chunks = 0, chunked_rows = 0;
