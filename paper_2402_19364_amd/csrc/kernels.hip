@@ -19,9 +19,9 @@
 //                |code| for scaled formats).
 //   norm pass    fixed-order FP64 reduction of the block partials per column.
 //
-// Lane layout: every lane owns 16 bytes of an X row (VEC elements), LPR =
-// KT / VEC lanes cover a row's column tile, a wave handles 64 / LPR rows at a
-// time.  Matrix entries and X rows are read with plain loads (X rows are
+// Lane layout: every lane owns 16 bytes of an X row (8 bytes for FP8), VEC
+// elements; LPR = KT / VEC lanes cover a row's column tile, a wave handles
+// 64 / LPR rows at a time.  Matrix entries and X rows are read with plain loads (X rows are
 // reused through L2 by neighbouring rows of the band); Y is written with
 // non-temporal stores.
 #include <hip/hip_runtime.h>
@@ -74,31 +74,6 @@ __device__ __forceinline__ uint32_t f32_to_f16(float f) {  // round to nearest e
     _Float16 h = (_Float16)f;
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
-// OCP E4M3FN: bias 7, subnormal quantum 2^-9, max 448.
-__device__ __forceinline__ float f8_to_f32(uint32_t code) {
-    uint32_t u = code & 0x7Fu;
-    float normal = __uint_as_float((u << 20) + (120u << 23));
-    float sub = (float)u * 0x1p-9f;
-    float a = u >= 8u ? normal : sub;
-    return (code & 0x80u) ? -a : a;
-}
-__device__ __forceinline__ uint32_t f32_to_f8(float f) {  // RNE, saturating to 448
-    uint32_t sign = (__float_as_uint(f) >> 24) & 0x80u;
-    float a = fminf(fabsf(f), 448.0f);
-    uint32_t code;
-    if (a >= 0x1p-6f) {
-        uint32_t u = __float_as_uint(a);
-        u += 0x7FFFFu + ((u >> 20) & 1u);
-        u &= ~0xFFFFFu;
-        uint32_t e = (u >> 23) - 120u;  // biased E4M3 exponent
-        code = (e << 3) | ((u >> 20) & 7u);
-        code = code > 0x7Eu ? 0x7Eu : code;
-    } else {
-        code = (uint32_t)__builtin_rintf(a * 512.0f);  // 0 .. 8 (8 = smallest normal)
-    }
-    return code | sign;
-}
-
 // One lane word at base + off: a wave-uniform base (SGPRs) plus a 32-bit
 // per-lane byte offset, so a gather costs one VGPR of address and no 64-bit math.
 template <class W, class O>
