@@ -143,6 +143,9 @@ def serving_bench(args):
     srv.run(closed, bypass=True)
     makespan = time.perf_counter() - t0
     mu = len(closed) / makespan
+    for r in closed:  # results go back to the allocator before the timed streams
+        r.result = None
+    torch.cuda.synchronize()
     log(f"[serving] closed loop: {len(closed)} requests in {makespan:.2f}s -> {mu:.1f} req/s")
     results = {}
     for frac in args.serving_load:
@@ -162,6 +165,9 @@ def serving_bench(args):
             "mean_ms": round(st["mean_ms"], 3),
             "GBps": round(sum(work_bytes(r) for r in done) / span / 1e9, 1)}
         log(f"[serving] load {frac:g}: {results[f'{frac:g}']}")
+        for r in done:
+            r.result = None
+        torch.cuda.synchronize()
     line = {
         "metric": "serving latency of iterated arrow-SpMM jobs (continuous batching)",
         "value": results["0.8" if "0.8" in results else f"{args.serving_load[0]:g}"]["p99_ms"],
