@@ -126,6 +126,17 @@ arrow_status_t arrow_decomp_level(arrow_decomp_t d, int32_t level, int64_t *n_i,
                                   const int64_t **row_ptr, const int32_t **col,
                                   const float **val);
 
+/*
+ * Counts of level `level`: positions n_i, entries nnz_i, entries in the head
+ * rows (position < b), in the head columns of the other rows (column < b) and
+ * in the band (both >= b), and rows holding entries.  Host only.
+ */
+typedef struct {
+    int64_t n_i, nnz_i, head_row_nnz, head_col_nnz, band_nnz, active_rows;
+} arrow_level_stats_t;
+arrow_status_t arrow_decomp_level_stats(arrow_decomp_t d, int32_t level,
+                                        arrow_level_stats_t *out);
+
 /* Versioned binary file with a checksum; load rejects corrupt files (ARROW_ERR_IO). */
 arrow_status_t arrow_decomp_save(arrow_decomp_t d, const char *path);
 arrow_status_t arrow_decomp_load(const char *path, arrow_decomp_t *out);
@@ -165,6 +176,9 @@ typedef struct {
 } arrow_plan_info_t;
 
 arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);
+/* Device memory owned by the plan (the plan's own buffers, allocated with
+ * hipMalloc at creation and freed by arrow_plan_destroy). */
+arrow_status_t arrow_plan_footprint(arrow_plan_t p, size_t *bytes);
 
 /*
  * Gather batch of a row pass (kernel = ARROW_KERNEL_UPPER or

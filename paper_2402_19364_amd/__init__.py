@@ -57,6 +57,8 @@ def _load():
         "arrow_decomp_load": [ctypes.c_char_p, pp],
         "arrow_plan_create": [P, I32, P, pp],
         "arrow_plan_info": [P, P],
+        "arrow_plan_footprint": [P, ctypes.POINTER(SZ)],
+        "arrow_decomp_level_stats": [P, I32, P],
         "arrow_plan_kernel_bytes": [P, I32, I64, I32, ctypes.POINTER(I64)],
         "arrow_workspace_size": [P, I64, I32, ctypes.POINTER(SZ)],
         "arrow_iterate_workspace_size": [P, I64, I32, ctypes.POINTER(SZ)],
@@ -113,6 +115,11 @@ class _DecompOpts(ctypes.Structure):
 class _DecompInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("b", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
+class _LevelStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("n_i", "nnz_i", "head_row_nnz", "head_col_nnz",
+                                              "band_nnz", "active_rows")]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -221,6 +228,12 @@ class Decomposition:
                     col=arr(col, nnz.value, ctypes.c_int32, np.int32),
                     val=arr(val, nnz.value, ctypes.c_float, np.float32))
 
+    def level_stats(self, i: int) -> dict:
+        """Counts of level i: n_i, nnz_i, head-row, head-column and band entries, active rows."""
+        st = _LevelStats()
+        _check(_load().arrow_decomp_level_stats(self._h, i, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _LevelStats._fields_}
+
     def levels(self) -> list:
         return [self.level(i) for i in range(self.info()["levels"])]
 
@@ -276,6 +289,12 @@ class Plan:
     def set_batch(self, kernel: int, batch: int) -> None:
         """Gather batch of KERNEL_UPPER / KERNEL_LEVEL0: -1 automatic, 0 wide, 4..8 short."""
         _check(_load().arrow_plan_set_batch(self._h, kernel, batch))
+
+    def footprint(self) -> int:
+        """Device bytes owned by the plan."""
+        out = ctypes.c_size_t()
+        _check(_load().arrow_plan_footprint(self._h, ctypes.byref(out)))
+        return out.value
 
     def kernel_bytes(self, kernel: int, k: int, dtype="f32") -> int:
         out = ctypes.c_int64()

@@ -139,6 +139,37 @@ arrow_status_t arrow_decomp_info(arrow_decomp_t d, arrow_decomp_info_t *out) {
     return ARROW_OK;
 }
 
+arrow_status_t arrow_decomp_level_stats(arrow_decomp_t d, int32_t level,
+                                        arrow_level_stats_t *out) {
+    if (!d || !out) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (level < 0 || level >= (int32_t)d->d.levels.size()) {
+        set_error("level out of range");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const arrow::Level &L = d->d.levels[level];
+    const int64_t b = d->d.b;
+    arrow_level_stats_t st{};
+    st.n_i = L.n_i;
+    st.nnz_i = (int64_t)L.col.size();
+    for (int64_t q = 0; q < L.n_i; ++q) {
+        const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
+        st.active_rows += e1 > e0;
+        for (int64_t e = e0; e < e1; ++e) {
+            if (q < b)
+                ++st.head_row_nnz;
+            else if (L.col[e] < b)
+                ++st.head_col_nnz;
+            else
+                ++st.band_nnz;
+        }
+    }
+    *out = st;
+    return ARROW_OK;
+}
+
 arrow_status_t arrow_decomp_level(arrow_decomp_t d, int32_t level, int64_t *n_i, int64_t *nnz_i,
                                   const int32_t **vertex_of_pos, const int64_t **row_ptr,
                                   const int32_t **col, const float **val) {
@@ -260,6 +291,15 @@ arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out) {
     out->fused_rows = P.fused_rows;
     out->level0_block_rows = P.l0_rpb;
     out->reserved = 0;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_plan_footprint(arrow_plan_t p, size_t *bytes) {
+    if (!p || !bytes) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    *bytes = (size_t)p->p->footprint;
     return ARROW_OK;
 }
 

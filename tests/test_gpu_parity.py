@@ -37,6 +37,7 @@ def _check_trajectory(M, b, k, T, seed_x=7, la=0, decomp_seed=1, ld=None, label=
     D.validate(M, levels, b)
     vop0 = levels[0]["vop"].astype(np.int64)
     plan = A_.Plan(d)
+    assert plan.footprint() == plan.info()["footprint_bytes"] > 0 or M.nnz == 0
     X0 = W.features(M.n, k, seed_x)
     ldx = ld or k
     xs = torch.zeros((M.n, ldx), dtype=torch.float32, device="cuda")

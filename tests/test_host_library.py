@@ -139,6 +139,28 @@ def test_error_paths():
     assert "max_levels" in msg
 
 
+def test_level_stats_match_the_exported_levels():
+    M = W.make_matrix("rmat", 12, "row_normalized", 1, 2, 16)
+    b = 48
+    d = _lib_decompose(M, b, seed=3)
+    total = 0
+    for i, L in enumerate(d.levels()):
+        st = d.level_stats(i)
+        rp, col = L["row_ptr"], L["col"].astype(np.int64)
+        rows = np.repeat(np.arange(L["n_i"]), np.diff(rp))
+        head_row = int(np.sum(rows < b))
+        head_col = int(np.sum((rows >= b) & (col < b)))
+        band = int(np.sum((rows >= b) & (col >= b)))
+        assert st == {"n_i": L["n_i"], "nnz_i": len(col), "head_row_nnz": head_row,
+                      "head_col_nnz": head_col, "band_nnz": band,
+                      "active_rows": int(np.count_nonzero(np.diff(rp)))}, i
+        assert np.all(np.abs(col[(rows >= b) & (col >= b)] - rows[(rows >= b) & (col >= b)]) <= b)
+        total += st["nnz_i"]
+    assert total == M.nnz
+    with pytest.raises(A_.ArrowError):
+        d.level_stats(len(d.levels()))
+
+
 def test_gather_batch_rule():
     # smallest short batch (4..8) holding all entries of >= 99% of the rows
     assert A_.csr_batch(W.make_matrix("grid2d", 30, "uniform", 0, 1).row_ptr) == 5
