@@ -9,7 +9,6 @@ namespace arrow {
 
 enum : int { kF32 = 0, kF16 = 1, kBF16 = 2, kF8E4M3 = 3 };
 enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
-constexpr int kNumXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
 constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
 constexpr int kStageLists = 512;     // listed partial rows staged in LDS per block

@@ -203,14 +203,12 @@ __device__ __forceinline__ float pow2_ceil(double x) {
     return (float)ldexp(1.0, e);
 }
 
-// Workgroup -> row block, keeping each XCD on a contiguous range of blocks:
-// dispatch places workgroup w on XCD w % 8, so XCD x receives the blocks
-// [x*q + min(x, r), ...) in order and its L2 sees neighbouring rows of the band.
-__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
-    const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
-    const int x = bid % kNumXcd, j = bid / kNumXcd;
-    return x * q + (x < r ? x : r) + j;
-}
+// Workgroup -> row block: workgroup w takes block w.  Dispatch places
+// workgroup w on XCD w % 8, so the eight XCDs work on one narrow stretch of
+// consecutive blocks at a time and share its band window of X through the
+// Infinity Cache; giving each XCD a contiguous range of its own instead
+// measured slower (3% on a 2048^2 grid, 17% on R-MAT 2^22).
+__device__ __forceinline__ int row_block(int bid) { return bid; }
 
 // ---------------------------------------------------------------------------
 // row kernel
@@ -258,7 +256,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     __shared__ int32_t s_fcol[FAR ? kStageEntries : 1];
     __shared__ int32_t s_fb[2];
 
-    const int wg = xcd_block(blockIdx.x, gridDim.x);
+    const int wg = row_block(blockIdx.x);
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave = tid / kWave;
@@ -644,7 +642,7 @@ __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, Tile t
     constexpr int UNR = PER < 8 ? PER : 8;
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
-    const int wg = xcd_block(blockIdx.x, gridDim.x);
+    const int wg = row_block(blockIdx.x);
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const int g = lane / LPR;

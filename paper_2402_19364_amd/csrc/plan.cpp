@@ -349,8 +349,8 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     }
     p.n_chunks = (int64_t)ch_ptr.size() - 1;
     // Run the chunks in order of their first column, not row by row: the hub
-    // rows' chunks that cover the same stretch of columns then run together
-    // (each XCD takes a contiguous range), so their X gathers share L2.  Only
+    // rows' chunks that cover the same stretch of columns then run together,
+    // so their X gathers share the caches.  Only
     // the storage moves: chunk c's partial row sits at n_up + chunk_slot[c]
     // and every list keeps its order, so the sums are unchanged.
     std::vector<int32_t> chunk_slot(p.n_chunks);
