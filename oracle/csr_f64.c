@@ -28,6 +28,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the row loops below (timing of the oracle on fewer cores). */
+void oracle_set_num_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* Y (n x k, row-major, ld k) = A (CSR, n x n) * X (n x k, row-major, ld k). */
 void oracle_csr_spmm_f64(int64_t n, const int64_t *row_ptr, const int32_t *col,
                          const float *val, const double *X, int64_t k, double *Y) {

@@ -321,8 +321,14 @@ def random_forest_arrangement(n, verts_mask, eu, ev, seed, level):
     return tree_order, singles
 
 
-def la_decompose(csr, b: int, seed: int = 0, la: str = "random_forest"):
-    """Reference LA-Decompose.  Returns the list of levels (see module doc)."""
+def la_decompose(csr, b: int, seed: int = 0, la: str = "random_forest", trace=None):
+    """Reference LA-Decompose.  Returns the list of levels (see module doc).
+
+    If `trace` is a list, one dict per level is appended to it: the head
+    vertices, the full position map `pos` (vertex -> position in pi_i, all n
+    vertices) and the undirected edges (u < v) of G'_i, the graph on the
+    non-head vertices (empty for the final vertex-cover level).  Tests use it
+    to check the counting step of the LA-Decompose lemma."""
     if b < 2:
         raise ValueError("arrow width b must be >= 2")
     n = csr.n
@@ -375,6 +381,13 @@ def la_decompose(csr, b: int, seed: int = 0, la: str = "random_forest"):
         keep = in_arrow(p, q, b)
         if final:
             assert np.all(keep)
+        if trace is not None:
+            if final:
+                gu = gv = np.zeros(0, dtype=np.int64)
+            else:
+                gu, gv = eu[keep_e], ev[keep_e]
+            trace.append(dict(head=np.asarray(head, dtype=np.int64), pos=pos.copy(),
+                              gu=gu.astype(np.int64), gv=gv.astype(np.int64), final=final))
         kp, kq, kv = p[keep], q[keep], val[keep]
         if level == 0:
             n_i = n

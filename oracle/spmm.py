@@ -41,12 +41,19 @@ def _load():
         lib.oracle_csr_spmm_rows_f64.argtypes = [p, p, p, p, i64, p, i64, p]
         lib.oracle_col_sumsq_f64.argtypes = [i64, i64, p, p]
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the oracle's row loops (for timing it on fewer cores)."""
+    _load().oracle_set_num_threads(int(t))
 
 
 def _ptr(a: np.ndarray) -> int:

@@ -1,0 +1,146 @@
+"""More pins of the oracle (CPU only): the error metric behind every parity
+gate, the storage spacing behind the element-wise precision bound, and the
+counting step of the LA-Decompose lemma (Section 5.1)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import decomp as D
+from oracle import quant as Q
+from oracle import spmm as S
+
+
+# ---------------------------------------------------------------------------
+# relative Frobenius error: values fixed by hand
+# ---------------------------------------------------------------------------
+
+def test_rel_fro_hand_values():
+    # ||a - ref||_F = 3, ||ref||_F = 4 (a missing square root would give 9/16)
+    assert S.rel_fro([[3.0, 0.0], [0.0, 4.0]], [[0.0, 0.0], [0.0, 4.0]]) == 0.75
+    # 3-4-5 triangle across two entries: ||(3, 4)|| / ||(0, 12) + (5, 0)|| = 5 / 13
+    assert math.isclose(S.rel_fro([[8.0], [16.0]], [[5.0], [12.0]]), 5.0 / 13.0,
+                        rel_tol=0, abs_tol=1e-16)
+    # every entry counts: an error in the second column alone
+    assert math.isclose(S.rel_fro([[1.0, 2.0], [0.0, 0.0]], [[1.0, 0.0], [0.0, 0.0]]), 2.0,
+                        rel_tol=0, abs_tol=1e-16)
+
+
+def test_rel_fro_scaled_copy_and_zero_reference():
+    rng = np.random.default_rng(3)
+    ref = rng.standard_normal((50, 7))
+    for c in (0.0, 0.5, 1.0, 1.25, -1.0):
+        assert math.isclose(S.rel_fro(c * ref, ref), abs(c - 1.0), rel_tol=1e-14, abs_tol=1e-15)
+    # zero reference: the absolute error (0 / 0 -> 0)
+    z = np.zeros((4, 3))
+    assert S.rel_fro(z, z) == 0.0
+    a = np.zeros((4, 3))
+    a[1, 2] = -2.0
+    assert S.rel_fro(a, z) == 2.0
+    # symmetric in the sign of the difference, not in its arguments
+    assert S.rel_fro(ref + 1.0, ref) == S.rel_fro(ref - 1.0, ref)
+
+
+# ---------------------------------------------------------------------------
+# storage spacing: exact powers of two from the format definitions
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fmt,x,expect", [
+    ("f16", 1.0, 2.0 ** -10),          # 10 fraction bits
+    ("f16", 1.5, 2.0 ** -10),
+    ("f16", 2.0, 2.0 ** -9),           # the binade above a power of two
+    ("f16", 65504.0, 32.0),            # largest finite, binade [2^15, 2^16)
+    ("f16", 6.1e-5, 2.0 ** -24),       # below 2^-14: subnormal spacing
+    ("f16", 2.0 ** -14, 2.0 ** -24),   # smallest normal
+    ("bf16", 3.0, 2.0 ** -6),          # 7 fraction bits, binade [2, 4)
+    ("bf16", 1.0, 2.0 ** -7),
+    ("bf16", -0.75, 2.0 ** -8),        # sign does not matter
+    ("f8e4m3", 448.0, 32.0),           # 3 fraction bits, binade [256, 512)
+    ("f8e4m3", 1.0, 2.0 ** -3),
+    ("f8e4m3", 0.001, 2.0 ** -9),      # below 2^-6: subnormal spacing
+    ("f8e4m3", 2.0 ** -6, 2.0 ** -9),
+    ("f8e4m3", 0.0, 2.0 ** -9),
+])
+def test_spacing_hand_values(fmt, x, expect):
+    assert float(Q.spacing(np.array([x]), fmt)[0]) == expect
+
+
+def test_spacing_f16_matches_numpy():
+    # numpy's spacing of IEEE binary16 (a library routine), on positive values
+    rng = np.random.default_rng(1)
+    x = np.concatenate([np.exp(rng.uniform(np.log(1e-7), np.log(6.0e4), 20000)),
+                        2.0 ** np.arange(-24, 16, dtype=np.float64)]).astype(np.float16)
+    x = x[(x > 0) & np.isfinite(x)]
+    ref = np.spacing(x).astype(np.float64)
+    got = Q.spacing(x.astype(np.float64), "f16")
+    assert np.array_equal(got, ref)
+
+
+def test_spacing_is_the_gap_between_codes():
+    # consecutive positive finite codes differ by exactly the spacing of the lower one
+    for fmt, codes in (("f8e4m3", np.arange(0, 0x7E, dtype=np.uint8)),
+                       ("f16", np.arange(0, 0x7BFF, dtype=np.uint16)),
+                       ("bf16", np.arange(0, 0x7F7F, 7, dtype=np.uint16))):
+        lo = Q.decode(codes, fmt)
+        hi = Q.decode(codes + 1, fmt)
+        assert np.array_equal(hi - lo, Q.spacing(lo, fmt)), fmt
+
+
+# ---------------------------------------------------------------------------
+# Section 5.1, LA-Decompose lemma: the counting (Markov) step.  In level i the
+# edges of G'_i farther than b from the diagonal number at most
+# lambda_{pi'_i}(G'_i) / (b + 1), and they are exactly the edges left to the
+# next levels (every edge at a head vertex, and every band edge, lands in B_i).
+# ---------------------------------------------------------------------------
+
+def _remaining_edges(levels, start, n):
+    """Undirected off-diagonal vertex pairs stored in levels >= start."""
+    keys = []
+    for L in levels[start:]:
+        vop = np.asarray(L["vop"], dtype=np.int64)
+        rp = np.asarray(L["row_ptr"], dtype=np.int64)
+        p = np.repeat(np.arange(L["n_i"], dtype=np.int64), np.diff(rp))
+        u, v = vop[p], vop[np.asarray(L["col"], dtype=np.int64)]
+        off = u != v
+        a, c = np.minimum(u[off], v[off]), np.maximum(u[off], v[off])
+        keys.append(a * n + c)
+    return np.unique(np.concatenate(keys)) if keys else np.zeros(0, dtype=np.int64)
+
+
+def _lemma_graphs():
+    out = [("rmat10", W.make_matrix("rmat", 10, "row_normalized", 21, 22, 16), 8),
+           ("rmat10_b32", W.make_matrix("rmat", 10, "row_normalized", 23, 24, 16), 32),
+           ("grid2d_24", W.make_matrix("grid2d", 24, "uniform", 25, 26), 4),
+           ("grid3d_8", W.make_matrix("grid3d", 8, "uniform", 27, 28), 6),
+           ("random_300", W.random_graph(300, 0.03, 29, diagonal=True), 5)]
+    return out
+
+
+@pytest.mark.parametrize("la", ["random_forest", "identity"])
+@pytest.mark.parametrize("case", range(5))
+def test_la_decompose_lemma_counting_step(case, la):
+    name, A, b = _lemma_graphs()[case]
+    trace = []
+    levels = D.la_decompose(A, b, seed=7, la=la, trace=trace)
+    D.validate(A, levels, b)
+    assert len(trace) == len(levels)
+    n = A.n
+    checked = 0
+    for i, tr in enumerate(trace):
+        if tr["final"]:
+            continue
+        pos = tr["pos"]
+        head = set(int(h) for h in tr["head"])
+        gu, gv = tr["gu"], tr["gv"]
+        assert not any(int(u) in head or int(v) in head for u, v in zip(gu, gv))
+        dist = np.abs(pos[gu] - pos[gv])
+        lam = int(dist.sum())                     # lambda_{pi'_i}(G'_i)
+        far = dist > b
+        # Markov: (b + 1) * #far <= sum of distances
+        assert int(far.sum()) * (b + 1) <= lam, (name, i)
+        # the far edges are exactly what the later levels hold
+        want = np.unique(np.minimum(gu[far], gv[far]) * n + np.maximum(gu[far], gv[far]))
+        assert np.array_equal(_remaining_edges(levels, i + 1, n), want), (name, i)
+        checked += 1
+    assert checked >= 1
