@@ -8,15 +8,15 @@
  * (problem statement of Section 2, "Matrices": X_{t+1} = sigma(A X_t) with
  * sigma a per-column normalisation) over an arrow matrix decomposition
  *
- *     A = sum_i P_{pi_i} B_i P_{pi_i}^T                       (Section 3, Eq. (1))
+ *     A = sum_i P_{pi_i} B_i P_{pi_i}^T                       (Section 4, Eq. (1))
  *
  * where every B_i has arrow width b: its nonzeros lie in the first b rows, the
  * first b columns, or the band |p - q| <= b (Section 1, 0-based here).
  *
  * Two stages:
- *   1. arrow_decompose (host, C++): LA-Decompose of Section 4.1 with the
- *      random spanning forest linear arrangement of Section 4.3 and the
- *      smallest-first tree order of Section 4.4.
+ *   1. arrow_decompose (host, C++): LA-Decompose of Section 5.1 with the
+ *      random spanning forest linear arrangement of Section 5.3 and the
+ *      smallest-first tree order of Section 5.4.
  *   2. arrow_plan_create uploads the decomposition to one GPU; arrow_spmm /
  *      arrow_spmm_iterate run the product with hand-written HIP kernels.
  *
@@ -74,7 +74,7 @@ enum {
 /* Linear arrangement used for the non-head vertices of each level. */
 typedef int32_t arrow_la_t;
 enum {
-    ARROW_LA_RANDOM_FOREST = 0, /* random spanning forest + smallest-first order (Sections 4.3-4.4) */
+    ARROW_LA_RANDOM_FOREST = 0, /* random spanning forest + smallest-first order (Sections 5.3-5.4) */
     ARROW_LA_IDENTITY = 1       /* vertices in id order (the input's own ordering) */
 };
 
@@ -86,22 +86,24 @@ typedef struct arrow_plan_s *arrow_plan_t;     /* device-resident object */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    int32_t b;          /* arrow width, >= 2 (Section 4.1 requires b >= 2) */
+    int32_t b;          /* arrow width, >= 2 (Section 5.1 requires b >= 2) */
     arrow_la_t la;      /* linear arrangement kind */
-    uint64_t seed;      /* seed of the random edge weights (Section 4.3, step 1) */
+    uint64_t seed;      /* seed of the random edge weights (Section 5.3, step 1) */
     int32_t max_levels; /* 0 = unlimited; otherwise fail with ARROW_ERR_UNSUPPORTED above it */
-    int32_t reserved;
+    int32_t threads;    /* host threads: 0 = every hardware thread, >= 1 = that many; the
+                           result does not depend on it */
 } arrow_decompose_opts_t;
 
 /*
- * LA-Decompose (Section 4.1) of the square n x n CSR matrix (host arrays):
+ * LA-Decompose (Section 5.1) of the square n x n CSR matrix (host arrays):
  * row_ptr int64[n+1], col int32[nnz] strictly increasing within each row and
  * < n, val float32[nnz]; nnz < 2^31.  The pattern is symmetrised for the graph
  * steps (degrees, spanning forest); every stored entry keeps its own value and
  * lands in exactly one level.  Level 0 spans all n positions; later levels are
- * compacted to the positions that hold entries (Section 3, "collect the
- * non-zeros at the top").  The result depends only on the inputs and opts.
- * Errors: ARROW_ERR_INVALID_ARG for a malformed CSR or b < 2.
+ * compacted to the positions that hold entries (Section 4, "collect the
+ * non-zeros at the top").  The result depends only on the inputs, b, la and
+ * seed (bit for bit, whatever opts.threads is).
+ * Errors: ARROW_ERR_INVALID_ARG for a malformed CSR, b < 2 or threads < 0.
  */
 arrow_status_t arrow_decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
                                const float *val, const arrow_decompose_opts_t *opts,
@@ -147,8 +149,24 @@ void arrow_decomp_destroy(arrow_decomp_t d);
 /* ------------------------------------------------------------------------ */
 
 /*
+ * Device allocator of plan buffers (process-wide).  alloc returns `bytes` of
+ * device memory of the current HIP device (the plan's; 256-byte aligned) or
+ * NULL on failure; `stream` is the stream given to arrow_plan_create.  free
+ * releases a pointer alloc returned, with stream = NULL: the caller destroys
+ * a plan only after its last product finished.  A plan keeps the allocator
+ * it was created with and frees through it.  arrow_set_allocator(NULL, NULL,
+ * NULL) restores the default (hipMalloc / hipFree).  Both functions or
+ * neither must be given (else ARROW_ERR_INVALID_ARG).  Not thread-safe
+ * against a concurrent arrow_plan_create.  Workspaces, X and Y are always the
+ * caller's; this hook covers the only device memory the library owns.
+ */
+typedef void *(*arrow_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*arrow_free_fn)(void *ptr, void *stream, void *ctx);
+arrow_status_t arrow_set_allocator(arrow_alloc_fn alloc, arrow_free_fn free_fn, void *ctx);
+
+/*
  * Upload a decomposition to GPU `device` as a plan (the arrow tiles of
- * Section 3.1 become row blocks of work; the level maps pi_i become
+ * Section 4.1 become row blocks of work; the level maps pi_i become
  * precomputed gather indices into the level-0 order).  Short rows of levels
  * >= 1 are folded into the level-0 row of their vertex (the products of
  * Alg. 2 reassociated per vertex); long rows of any level become chunks with
@@ -176,8 +194,9 @@ typedef struct {
 } arrow_plan_info_t;
 
 arrow_status_t arrow_plan_info(arrow_plan_t p, arrow_plan_info_t *out);
-/* Device memory owned by the plan (the plan's own buffers, allocated with
- * hipMalloc at creation and freed by arrow_plan_destroy). */
+/* Device memory owned by the plan (the plan's own buffers, allocated through
+ * the allocator of arrow_set_allocator at creation and freed by
+ * arrow_plan_destroy). */
 arrow_status_t arrow_plan_footprint(arrow_plan_t p, size_t *bytes);
 
 /*

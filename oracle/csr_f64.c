@@ -1,9 +1,9 @@
 /*
  * ORACLE (test infrastructure only).  Plain FP64 CSR sparse x dense product.
  *
- * The arrow decomposition is an exact rewriting of A (Section 3, Eq. (1):
+ * The arrow decomposition is an exact rewriting of A (Section 4, Eq. (1):
  * A X = sum_i P_i (B_i (P_i^T X)), and every nonzero of A lands in exactly one
- * B_i, Section 5 storage lemma).  The method therefore reaches Y = A X up to
+ * B_i, Section 6.2 storage lemma).  The method therefore reaches Y = A X up to
  * rounding order, and this file is that plain definition written out:
  *
  *     Y[i, :] = sum over stored entries p of row i of  val[p] * X[col[p], :]

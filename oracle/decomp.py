@@ -14,15 +14,15 @@ Validator (pinned: exact invariants, brute-force dense check, worked example
 of Fig. 3):
 
 1. every map is injective into [0, n); level 0 is a bijection on [0, n)
-   (the decomposition of Section 3 uses full permutations P_{pi_i}),
+   (the decomposition of Section 4 uses full permutations P_{pi_i}),
 2. every stored (p, q) of B_i satisfies the arrow-width predicate of
    Section 1 (0-based: p < b or q < b or |p - q| <= b),
 3. the multiset {(vop_i[p], vop_i[q], bits(v))} over all levels equals the
-   multiset of A's stored entries (every entry in exactly one B_i, Section 3
-   Eq. (1) and the storage lemma of Section 5).
+   multiset of A's stored entries (every entry in exactly one B_i, Section 4
+   Eq. (1) and the storage lemma of Section 6.2).
 
-Reference LA-Decompose (Section 4.1) with random spanning forest linear
-arrangements (Section 4.3) and smallest-first tree order (Section 4.4), with
+Reference LA-Decompose (Section 5.1) with random spanning forest linear
+arrangements (Section 5.3) and smallest-first tree order (Section 5.4), with
 the readings of the points the paper leaves open:
 
 * degrees are taken in the undirected graph G_i of the symmetrised remaining
@@ -45,7 +45,7 @@ the readings of the points the paper leaves open:
   at most b vertices and holds every leftover edge;
 * level 0 always spans all n positions; later levels are compacted to
   n_i = 1 + the largest position holding an entry (the non-zeros are
-  collected at the top, Section 3).
+  collected at the top, Section 4).
 """
 from __future__ import annotations
 
@@ -250,7 +250,7 @@ def kruskal_forest(n, eu, ev, keys):
 
 
 def smallest_first_order(vertices, tree_edges):
-    """Smallest-first layout of one tree (Section 4.4): the root first, then
+    """Smallest-first layout of one tree (Section 5.4): the root first, then
     the child subtrees one after the other in increasing size (ties by child
     id), each laid out recursively.  Root = smallest vertex id."""
     adj = {v: [] for v in vertices}
@@ -281,7 +281,7 @@ def smallest_first_order(vertices, tree_edges):
 
 
 def random_forest_arrangement(n, verts_mask, eu, ev, seed, level):
-    """Random spanning forest linear arrangement (Section 4.3) of the graph on
+    """Random spanning forest linear arrangement (Section 5.3) of the graph on
     the vertices where verts_mask is true.  Returns (tree vertex order,
     singleton vertices) -- trees of >= 2 vertices in decreasing size (ties by
     root id), each in smallest-first order."""

@@ -56,6 +56,7 @@ def _load():
         "arrow_decomp_save": [P, ctypes.c_char_p],
         "arrow_decomp_load": [ctypes.c_char_p, pp],
         "arrow_plan_create": [P, I32, P, pp],
+        "arrow_set_allocator": [P, P, P],
         "arrow_plan_info": [P, P],
         "arrow_plan_footprint": [P, ctypes.POINTER(SZ)],
         "arrow_decomp_level_stats": [P, I32, P],
@@ -109,7 +110,7 @@ def _check(status: int):
 
 class _DecompOpts(ctypes.Structure):
     _fields_ = [("b", ctypes.c_int32), ("la", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("max_levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_levels", ctypes.c_int32), ("threads", ctypes.c_int32)]
 
 
 class _DecompInfo(ctypes.Structure):
@@ -168,20 +169,21 @@ def _stream_handle(stream=None) -> Optional[int]:
 # ---------------------------------------------------------------------------
 
 class Decomposition:
-    """Host-side arrow decomposition (LA-Decompose, Section 4.1)."""
+    """Host-side arrow decomposition (LA-Decompose, Section 5.1)."""
 
     def __init__(self, handle: int):
         self._h = ctypes.c_void_p(handle)
 
     @classmethod
     def from_csr(cls, n: int, row_ptr, col, val, b: int, seed: int = 0,
-                 la: int = LA_RANDOM_FOREST, max_levels: int = 0) -> "Decomposition":
+                 la: int = LA_RANDOM_FOREST, max_levels: int = 0,
+                 threads: int = 0) -> "Decomposition":
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         c = np.ascontiguousarray(col, dtype=np.int32)
         v = np.ascontiguousarray(val, dtype=np.float32)
         if rp.shape[0] != n + 1:
             raise ValueError("row_ptr must have n + 1 entries")
-        opts = _DecompOpts(b, la, seed & ((1 << 64) - 1), max_levels, 0)
+        opts = _DecompOpts(b, la, seed & ((1 << 64) - 1), max_levels, threads)
         h = ctypes.c_void_p()
         _check(_load().arrow_decompose(n, _np_ptr(rp), _np_ptr(c) if c.size else None,
                                        _np_ptr(v) if v.size else None, ctypes.byref(opts),
@@ -190,8 +192,8 @@ class Decomposition:
 
     @classmethod
     def from_matrix(cls, A, b: int, seed: int = 0, la: int = LA_RANDOM_FOREST,
-                    max_levels: int = 0) -> "Decomposition":
-        return cls.from_csr(A.n, A.row_ptr, A.col, A.val, b, seed, la, max_levels)
+                    max_levels: int = 0, threads: int = 0) -> "Decomposition":
+        return cls.from_csr(A.n, A.row_ptr, A.col, A.val, b, seed, la, max_levels, threads)
 
     @classmethod
     def load(cls, path: str) -> "Decomposition":
@@ -247,6 +249,58 @@ class Decomposition:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# device allocator of plan buffers
+# ---------------------------------------------------------------------------
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_keep = None  # the installed callbacks (ctypes needs them alive)
+
+
+def set_allocator(alloc=None, free=None) -> None:
+    """Install Python callables as the plan allocator: alloc(bytes, stream) ->
+    device pointer (int, 0 on failure), free(ptr).  Both None restores
+    hipMalloc / hipFree."""
+    global _allocator_keep
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check(_load().arrow_set_allocator(None, None, None))
+        _allocator_keep = None
+        return
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), stream or 0)) or None
+        except Exception:  # a failed allocation is reported as NULL
+            return None
+
+    def _f(ptr, stream, ctx):
+        try:
+            free(int(ptr))
+        except Exception:
+            pass
+
+    cb = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(_load().arrow_set_allocator(ctypes.cast(cb[0], ctypes.c_void_p),
+                                       ctypes.cast(cb[1], ctypes.c_void_p), None))
+    _allocator_keep = cb
+
+
+def use_torch_allocator() -> None:
+    """Plan buffers come from PyTorch's caching allocator (on the stream given
+    to the plan), so plans share the pool with tensors and destroying a plan
+    returns its memory to that pool without a device synchronisation."""
+    import torch
+
+    def alloc(nbytes, stream):
+        s = stream if stream else torch.cuda.current_stream().cuda_stream
+        return torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device(), s)
+
+    set_allocator(alloc, torch.cuda.caching_allocator_delete)
 
 
 # ---------------------------------------------------------------------------

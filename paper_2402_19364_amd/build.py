@@ -21,10 +21,11 @@ LIB = os.path.join(HERE, "libarrow.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "plan.cpp", "capi.cpp", "decompose.cpp", "decomp_io.cpp",
+SOURCES = ["kernels_f32.hip", "kernels_bf16.hip", "kernels_f16.hip", "kernels_f8e4m3.hip",
+           "kernels.hip", "plan.cpp", "capi.cpp", "decompose.cpp", "decomp_io.cpp",
            "baseline_rocsparse.cpp"]
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",
           "-Wno-unused-function"]
 # No packed FP32 instructions in device code.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
@@ -46,7 +47,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,

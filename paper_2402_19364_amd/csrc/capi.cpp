@@ -227,6 +227,19 @@ arrow_status_t arrow_decomp_load(const char *path, arrow_decomp_t *out) {
 
 void arrow_decomp_destroy(arrow_decomp_t d) { delete d; }
 
+arrow_status_t arrow_set_allocator(arrow_alloc_fn alloc, arrow_free_fn free_fn, void *ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("give both the alloc and the free function, or neither");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    arrow::Allocator a;
+    a.alloc = alloc;
+    a.free = free_fn;
+    a.ctx = alloc ? ctx : nullptr;
+    arrow::set_allocator(a);
+    return ARROW_OK;
+}
+
 arrow_status_t arrow_plan_create(arrow_decomp_t d, int32_t device, void *stream,
                                  arrow_plan_t *out) {
     if (!out) {

@@ -139,8 +139,24 @@ arrow_status_t load_decomp(const char *path, Decomp &out) {
             if (L.row_ptr[p + 1] < L.row_ptr[p]) return fail("row pointers");
         for (int64_t p = 0; p < L.n_i; ++p)
             if (L.vop[p] < 0 || L.vop[p] >= d.n) return fail("vertex map");
-        for (int64_t e = 0; e < nnz_i; ++e)
-            if (L.col[e] < 0 || L.col[e] >= L.n_i) return fail("column");
+        {
+            // the map of a level is injective (level 0: a permutation of [0, n))
+            std::vector<uint8_t> used(d.n, 0);
+            for (int64_t p = 0; p < L.n_i; ++p) {
+                if (used[L.vop[p]]) return fail("vertex map is not injective");
+                used[L.vop[p]] = 1;
+            }
+        }
+        const int64_t b = d.b;
+        for (int64_t p = 0; p < L.n_i; ++p)
+            for (int64_t e = L.row_ptr[p]; e < L.row_ptr[p + 1]; ++e) {
+                const int64_t q = L.col[e];
+                if (q < 0 || q >= L.n_i) return fail("column");
+                if (e > L.row_ptr[p] && q <= L.col[e - 1]) return fail("columns not increasing");
+                // arrow width b (Section 1): head row, head column or the band
+                if (!(p < b || q < b || (p > q ? p - q : q - p) <= b))
+                    return fail("entry outside the arrow shape");
+            }
         d.levels.push_back(std::move(L));
     }
     uint64_t expect = r.h, stored = 0;

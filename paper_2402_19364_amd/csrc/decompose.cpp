@@ -1,29 +1,38 @@
-// Host LA-Decompose (Section 4.1) with the random spanning forest linear
-// arrangement (Section 4.3) and smallest-first tree order (Section 4.4).
+// Host LA-Decompose (Section 5.1) with the random spanning forest linear
+// arrangement (Section 5.3) and smallest-first tree order (Section 5.4).
 //
 // Per level i, on the undirected graph G_i of the symmetrised remaining
 // pattern (self loops excluded):
 //   1. head H_i: the b vertices of positive degree with the largest degree
 //      (ties to the smaller id); they take positions 0 .. |H_i|-1,
 //   2. every edge of G_i - H_i gets a 64-bit random weight (counter-based
-//      SplitMix64 keyed by level and edge); Kruskal builds the unique minimum
-//      spanning forest, ties by (u, v),
+//      SplitMix64 keyed by level and edge: a bijection of the edge id, so the
+//      weights are distinct and the minimum spanning forest is unique);
+//      Boruvka rounds build it in parallel,
 //   3. each tree is rooted at its smallest id and laid out in smallest-first
 //      preorder (children by subtree size, then id); trees follow the head in
 //      decreasing size (ties: root id); then single vertices that still hold
 //      entries, then the rest, both by id,
 //   4. a stored entry (u, v) goes to B_i when its positions (p, q) satisfy
 //      p < b or q < b or |p - q| <= b, otherwise to A_{i+1}.
-// The loop runs while nnz(A_i) > 2b (Section 4.1), counted on the symmetrised
+// The loop runs while nnz(A_i) > 2b (Section 5.1), counted on the symmetrised
 // pattern; the leftover (at most b edges) becomes a last level whose head is a
 // greedy vertex cover (most uncovered edges first, ties by id).  Level 0 spans
 // all n positions; later levels keep positions [0, 1 + largest used).
+//
+// Every step runs on `threads` host threads (opts.threads, 0 = all) and gives
+// the same result for any thread count: parallel loops write disjoint ranges
+// at offsets from prefix sums, integer counts use atomic adds (order
+// independent), and whatever atomic scatter leaves unordered is sorted by a
+// unique key afterwards.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <numeric>
 #include <set>
 #include <string>
+#include <thread>
 
 #include "internal.h"
 
@@ -46,35 +55,55 @@ int bits_for(uint64_t maxval) {
     return b;
 }
 
-// Stable LSD radix sort of (key, payload) pairs by key, using only the low
-// `bits` bits of the key.
-void radix_sort(std::vector<uint64_t> &key, std::vector<uint32_t> &pay, int bits) {
-    const size_t m = key.size();
-    std::vector<uint64_t> k2(m);
-    std::vector<uint32_t> p2(m);
-    for (int shift = 0; shift < bits; shift += 8) {
-        size_t cnt[257] = {0};
-        for (size_t i = 0; i < m; ++i) ++cnt[((key[i] >> shift) & 0xFF) + 1];
-        for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
-        for (size_t i = 0; i < m; ++i) {
-            size_t dst = cnt[(key[i] >> shift) & 0xFF]++;
-            k2[dst] = key[i];
-            p2[dst] = pay[i];
-        }
-        key.swap(k2);
-        pay.swap(p2);
+// Runs fn(lo, hi, t) for t = 0 .. nt-1 over [0, count) split into contiguous
+// ranges of equal size (thread t takes the t-th range), on nt threads; small
+// counts run the same ranges one after the other on the calling thread.
+// Every t is called (possibly with an empty range), so per-thread results
+// are always written.
+template <class F>
+void par_for(int nt, int64_t count, F &&fn) {
+    if (nt <= 1 || count < 4096) {
+        for (int t = 0; t < std::max(nt, 1); ++t)
+            fn(count * t / std::max(nt, 1), count * (t + 1) / std::max(nt, 1), t);
+        return;
     }
+    std::vector<std::thread> ts;
+    ts.reserve(nt);
+    for (int t = 0; t < nt; ++t) {
+        const int64_t lo = count * t / nt, hi = count * (t + 1) / nt;
+        ts.emplace_back([&fn, lo, hi, t] { fn(lo, hi, t); });
+    }
+    for (auto &th : ts) th.join();
 }
 
-void radix_sort_keys(std::vector<uint64_t> &key, int bits) {
-    const size_t m = key.size();
-    std::vector<uint64_t> k2(m);
-    for (int shift = 0; shift < bits; shift += 8) {
-        size_t cnt[257] = {0};
-        for (size_t i = 0; i < m; ++i) ++cnt[((key[i] >> shift) & 0xFF) + 1];
-        for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
-        for (size_t i = 0; i < m; ++i) k2[cnt[(key[i] >> shift) & 0xFF]++] = key[i];
-        key.swap(k2);
+// Runs fn(t) for t = 0 .. nt-1, one thread each (tasks of uneven size).
+template <class F>
+void par_each(int nt, F &&fn) {
+    if (nt <= 1) {
+        fn(0);
+        return;
+    }
+    std::vector<std::thread> ts;
+    ts.reserve(nt);
+    for (int t = 0; t < nt; ++t) ts.emplace_back([&fn, t] { fn(t); });
+    for (auto &th : ts) th.join();
+}
+
+// Exclusive prefix sum of per-thread counts; returns the total.
+int64_t exclusive_scan(std::vector<int64_t> &c) {
+    int64_t s = 0;
+    for (auto &v : c) {
+        const int64_t x = v;
+        v = s;
+        s += x;
+    }
+    return s;
+}
+
+inline void atomic_min_u64(uint64_t *p, uint64_t v) {
+    uint64_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+    while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, true, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED)) {
     }
 }
 
@@ -82,21 +111,6 @@ struct Entries {  // remaining stored entries, in CSR order of A
     std::vector<int32_t> r, c;
     std::vector<float> v;
     size_t size() const { return r.size(); }
-};
-
-struct UnionFind {
-    std::vector<int32_t> parent;
-    explicit UnionFind(int64_t n) : parent(n) { std::iota(parent.begin(), parent.end(), 0); }
-    int32_t find(int32_t x) {
-        int32_t root = x;
-        while (parent[root] != root) root = parent[root];
-        while (parent[x] != root) {
-            int32_t nx = parent[x];
-            parent[x] = root;
-            x = nx;
-        }
-        return root;
-    }
 };
 
 // Smallest-first layouts of the trees of a forest over n vertices, trees in
@@ -227,7 +241,244 @@ std::vector<int32_t> greedy_cover(int64_t n, const std::vector<int32_t> &eu,
     return cover;
 }
 
+
+// Undirected edges {u, v} (u < v) of the pattern of the remaining entries
+// (sorted by (row, column)), sorted by (u, v) without duplicates; self loops
+// are counted in n_diag.  Entries with r < c already come in (u, v) order;
+// the others, keyed (c, r), are bucketed by ranges of c (per-thread counts,
+// stable scatter) and each bucket is sorted; the two sorted key lists are
+// then merged per range of u.
+void undirected_edges(int nt, int64_t n, const std::vector<int32_t> &R,
+                      const std::vector<int32_t> &C, std::vector<int32_t> &eu,
+                      std::vector<int32_t> &ev, int64_t &n_diag) {
+    const int64_t m = (int64_t)R.size();
+    const uint64_t un = (uint64_t)std::max<int64_t>(n, 1);
+    const int P = 64 * nt;  // buckets of list 2 by ranges of c
+    auto bucket_of = [&](int64_t c) { return (int)(c * P / std::max<int64_t>(n, 1)); };
+    std::vector<int64_t> c1(nt, 0), cd(nt, 0), h2((size_t)nt * P, 0);
+    par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+        int64_t a = 0, d = 0;
+        int64_t *h = &h2[(size_t)t * P];
+        for (int64_t e = lo; e < hi; ++e) {
+            if (R[e] < C[e])
+                ++a;
+            else if (R[e] > C[e])
+                ++h[bucket_of(C[e])];
+            else
+                ++d;
+        }
+        c1[t] = a, cd[t] = d;
+    });
+    n_diag = 0;
+    for (int t = 0; t < nt; ++t) n_diag += cd[t];
+    const int64_t m1 = exclusive_scan(c1);
+    // bucket-major, thread-minor offsets: a stable scatter
+    std::vector<int64_t> boff((size_t)nt * P), bstart(P + 1, 0);
+    {
+        int64_t s2 = 0;
+        for (int q = 0; q < P; ++q) {
+            bstart[q] = s2;
+            for (int t = 0; t < nt; ++t) {
+                boff[(size_t)t * P + q] = s2;
+                s2 += h2[(size_t)t * P + q];
+            }
+        }
+        bstart[P] = s2;
+    }
+    const int64_t m2 = bstart[P];
+    std::vector<uint64_t> k1(m1), k2(m2);
+    par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+        int64_t o = c1[t];
+        int64_t *bo = &boff[(size_t)t * P];
+        for (int64_t e = lo; e < hi; ++e) {
+            if (R[e] < C[e])
+                k1[o++] = (uint64_t)R[e] * un + (uint64_t)C[e];
+            else if (R[e] > C[e])
+                k2[bo[bucket_of(C[e])]++] = (uint64_t)C[e] * un + (uint64_t)R[e];
+        }
+    });
+    par_for(nt, P, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t q = lo; q < hi; ++q) std::sort(k2.begin() + bstart[q], k2.begin() + bstart[q + 1]);
+    });
+    // merge the two sorted lists per range of u, dropping duplicates
+    std::vector<int64_t> s1(nt + 1), s2(nt + 1), cnt(nt, 0);
+    for (int t = 0; t <= nt; ++t) {
+        const uint64_t key0 = (uint64_t)(n * t / nt) * un;
+        s1[t] = std::lower_bound(k1.begin(), k1.end(), key0) - k1.begin();
+        s2[t] = std::lower_bound(k2.begin(), k2.end(), key0) - k2.begin();
+    }
+    s1[nt] = m1;
+    s2[nt] = m2;
+    auto merge = [&](int t, bool write, int64_t o) {
+        int64_t i = s1[t], j = s2[t], k = 0;
+        uint64_t last = UINT64_MAX;
+        while (i < s1[t + 1] || j < s2[t + 1]) {
+            uint64_t x;
+            if (j >= s2[t + 1] || (i < s1[t + 1] && k1[i] <= k2[j]))
+                x = k1[i++];
+            else
+                x = k2[j++];
+            if (x == last) continue;
+            last = x;
+            if (write) {
+                eu[o + k] = (int32_t)(x / un);
+                ev[o + k] = (int32_t)(x % un);
+            }
+            ++k;
+        }
+        return k;
+    };
+    par_each(nt, [&](int t) { cnt[t] = merge(t, false, 0); });
+    const int64_t ne = exclusive_scan(cnt);
+    eu.resize(ne);
+    ev.resize(ne);
+    par_each(nt, [&](int t) { merge(t, true, cnt[t]); });
+}
+
+// Minimum spanning forest of the edges listed in `live` under the distinct
+// weights key[e], by Boruvka rounds: every component picks its lightest
+// outgoing edge (atomic minimum of the weight), the picked edges join the
+// forest and merge the components.  The forest is unique, so the result does
+// not depend on the thread count.  Returns the forest's edges in edge order.
+void boruvka_msf(int nt, int64_t n, const std::vector<int32_t> &eu,
+                 const std::vector<int32_t> &ev, const std::vector<uint64_t> &key,
+                 std::vector<int64_t> live, std::vector<int32_t> &fu,
+                 std::vector<int32_t> &fv) {
+    // per live edge: its index and the component labels of its endpoints
+    // (labels are vertex ids of the component roots)
+    int64_t m = (int64_t)live.size();
+    std::vector<int32_t> cu(m), cv(m);
+    par_for(nt, m, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i) {
+            cu[i] = eu[live[i]];
+            cv[i] = ev[live[i]];
+        }
+    });
+    std::vector<int32_t> parent(n);
+    std::vector<uint64_t> best(n, UINT64_MAX);
+    std::vector<int64_t> bedge(n, -1);
+    std::vector<uint8_t> in_forest(eu.size(), 0);
+    std::vector<int32_t> roots;  // labels touched this round
+    std::vector<int64_t> cnt(nt);
+    // compaction buffers, swapped with the live arrays every round (the live
+    // count only shrinks, so they never grow)
+    std::vector<int64_t> nlive(m);
+    std::vector<int32_t> ncu(m), ncv(m);
+    par_for(nt, n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t v = lo; v < hi; ++v) parent[v] = (int32_t)v;
+    });
+    while (m > 0) {
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t i = lo; i < hi; ++i) {
+                const uint64_t k = key[live[i]];
+                atomic_min_u64(&best[cu[i]], k);
+                atomic_min_u64(&best[cv[i]], k);
+            }
+        });
+        // the edge of each component's minimum (one writer: weights are distinct)
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t i = lo; i < hi; ++i) {
+                const uint64_t k = key[live[i]];
+                if (best[cu[i]] == k) bedge[cu[i]] = i;
+                if (best[cv[i]] == k) bedge[cv[i]] = i;
+            }
+        });
+        // link: a component points at the other end of its edge
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t i = lo; i < hi; ++i) {
+                if (bedge[cu[i]] == i) {
+                    parent[cu[i]] = cv[i];
+                    __atomic_store_n(&in_forest[live[i]], (uint8_t)1, __ATOMIC_RELAXED);
+                }
+                if (bedge[cv[i]] == i) {
+                    parent[cv[i]] = cu[i];
+                    __atomic_store_n(&in_forest[live[i]], (uint8_t)1, __ATOMIC_RELAXED);
+                }
+            }
+        });
+        // the labels linked this round, in increasing order
+        roots.clear();
+        {
+            std::vector<std::vector<int32_t>> part(nt);
+            par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+                for (int64_t i = lo; i < hi; ++i) {
+                    if (bedge[cu[i]] == i) part[t].push_back(cu[i]);
+                    if (bedge[cv[i]] == i) part[t].push_back(cv[i]);
+                }
+            });
+            for (auto &q : part) roots.insert(roots.end(), q.begin(), q.end());
+            std::sort(roots.begin(), roots.end());
+            roots.erase(std::unique(roots.begin(), roots.end()), roots.end());
+        }
+        const int64_t nr = (int64_t)roots.size();
+        // two components that picked the same edge point at each other: the
+        // smaller becomes the root
+        par_for(nt, nr, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t j = lo; j < hi; ++j) {
+                const int32_t v = roots[j], p = parent[v];
+                if (parent[p] == v && v < p) parent[v] = v;
+            }
+        });
+        // pointer jumping to the roots (only labels linked this round move)
+        for (bool changed = true; changed;) {
+            std::atomic<bool> ch{false};
+            par_for(nt, nr, [&](int64_t lo, int64_t hi, int) {
+                bool c = false;
+                for (int64_t j = lo; j < hi; ++j) {
+                    const int32_t v = roots[j], p = parent[v], g = parent[p];
+                    if (g != p) {
+                        parent[v] = g;
+                        c = true;
+                    }
+                }
+                if (c) ch = true;
+            });
+            changed = ch;
+        }
+        par_for(nt, nr, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t j = lo; j < hi; ++j) {
+                best[roots[j]] = UINT64_MAX;
+                bedge[roots[j]] = -1;
+            }
+        });
+        // relabel the edges, keep those between different components (in order)
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+            int64_t c = 0;
+            for (int64_t i = lo; i < hi; ++i) {
+                cu[i] = parent[cu[i]];
+                cv[i] = parent[cv[i]];
+                c += cu[i] != cv[i];
+            }
+            cnt[t] = c;
+        });
+        std::vector<int64_t> off(cnt);
+        const int64_t m2 = exclusive_scan(off);
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+            int64_t o = off[t];
+            for (int64_t i = lo; i < hi; ++i)
+                if (cu[i] != cv[i]) {
+                    nlive[o] = live[i];
+                    ncu[o] = cu[i];
+                    ncv[o] = cv[i];
+                    ++o;
+                }
+        });
+        live.swap(nlive);
+        cu.swap(ncu);
+        cv.swap(ncv);
+        m = m2;
+    }
+    fu.clear();
+    fv.clear();
+    for (size_t e = 0; e < eu.size(); ++e)
+        if (in_forest[e]) {
+            fu.push_back(eu[e]);
+            fv.push_back(ev[e]);
+        }
+}
+
 }  // namespace
+
 
 arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
                          const float *val, const arrow_decompose_opts_t &opts, Decomp &out) {
@@ -238,6 +489,10 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
     }
     if (opts.b < 2) {
         set_error("arrow width b must be >= 2");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (opts.threads < 0) {
+        set_error("threads must be >= 0 (0 = every hardware thread)");
         return ARROW_ERR_INVALID_ARG;
     }
     if (opts.la != ARROW_LA_RANDOM_FOREST && opts.la != ARROW_LA_IDENTITY) {
@@ -263,16 +518,31 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
         set_error("nnz must be < 2^31");
         return ARROW_ERR_INVALID_ARG;
     }
-    for (int64_t i = 0; i < n; ++i) {
-        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
-            if (col[p] < 0 || col[p] >= n) {
-                set_error("column index out of range in row " + std::to_string(i));
-                return ARROW_ERR_INVALID_ARG;
-            }
-            if (p > row_ptr[i] && col[p] <= col[p - 1]) {
-                set_error("columns must be strictly increasing within row " + std::to_string(i));
-                return ARROW_ERR_INVALID_ARG;
-            }
+    const int nt = opts.threads > 0
+                       ? opts.threads
+                       : (int)std::max(1u, std::min(256u, std::thread::hardware_concurrency()));
+    {
+        // the first bad row (the same message for every thread count)
+        std::vector<int64_t> bad_col(nt, INT64_MAX), bad_ord(nt, INT64_MAX);
+        par_for(nt, n, [&](int64_t lo, int64_t hi, int t) {
+            for (int64_t i = lo; i < hi; ++i)
+                for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                    if (col[p] < 0 || col[p] >= n) {
+                        if (bad_col[t] == INT64_MAX) bad_col[t] = i;
+                    } else if (p > row_ptr[i] && col[p] <= col[p - 1]) {
+                        if (bad_ord[t] == INT64_MAX) bad_ord[t] = i;
+                    }
+                }
+        });
+        const int64_t bc = *std::min_element(bad_col.begin(), bad_col.end());
+        const int64_t bo = *std::min_element(bad_ord.begin(), bad_ord.end());
+        if (bc != INT64_MAX && bc <= bo) {
+            set_error("column index out of range in row " + std::to_string(bc));
+            return ARROW_ERR_INVALID_ARG;
+        }
+        if (bo != INT64_MAX) {
+            set_error("columns must be strictly increasing within row " + std::to_string(bo));
+            return ARROW_ERR_INVALID_ARG;
         }
     }
     const int64_t b = opts.b;
@@ -287,13 +557,14 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
     rem.r.resize(nnz);
     rem.c.assign(col, col + nnz);
     rem.v.assign(val, val + nnz);
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) rem.r[p] = (int32_t)i;
+    par_for(nt, n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) rem.r[p] = (int32_t)i;
+    });
 
-    const uint64_t un = (uint64_t)std::max<int64_t>(n, 1);
-    const int key_bits = bits_for(un * un - 1);
     std::vector<uint8_t> is_head(n), has_entry(n), placed(n);
     std::vector<int32_t> pos(n);
+    std::vector<int64_t> tcnt(nt), tcnt2(nt), tmax(nt);
     for (int32_t level = 0;; ++level) {
         if (opts.max_levels > 0 && level >= opts.max_levels) {
             set_error("decomposition needs more than max_levels = " +
@@ -301,39 +572,24 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
             out = Decomp();
             return ARROW_ERR_UNSUPPORTED;
         }
-        const size_t m = rem.size();
+        const int64_t m = (int64_t)rem.size();
         // undirected edges of the remaining pattern, sorted by (u, v)
-        std::vector<uint64_t> ekey;
-        ekey.reserve(m);
+        std::vector<int32_t> eu, ev;
         int64_t n_diag = 0;
-        for (size_t e = 0; e < m; ++e) {
-            int32_t r = rem.r[e], c = rem.c[e];
-            if (r == c) {
-                ++n_diag;
-                continue;
-            }
-            uint64_t u = (uint64_t)std::min(r, c), v = (uint64_t)std::max(r, c);
-            ekey.push_back(u * un + v);
-        }
-        radix_sort_keys(ekey, key_bits);
-        ekey.erase(std::unique(ekey.begin(), ekey.end()), ekey.end());
-        const size_t ne = ekey.size();
-        std::vector<int32_t> eu(ne), ev(ne);
-        for (size_t e = 0; e < ne; ++e) {
-            eu[e] = (int32_t)(ekey[e] / un);
-            ev[e] = (int32_t)(ekey[e] % un);
-        }
-        std::vector<uint64_t>().swap(ekey);
+        undirected_edges(nt, n, rem.r, rem.c, eu, ev, n_diag);
+        const int64_t ne = (int64_t)eu.size();
         std::fill(has_entry.begin(), has_entry.end(), 0);
-        for (size_t e = 0; e < m; ++e) {
-            has_entry[rem.r[e]] = 1;
-            has_entry[rem.c[e]] = 1;
-        }
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t e = lo; e < hi; ++e) {
+                __atomic_store_n(&has_entry[rem.r[e]], (uint8_t)1, __ATOMIC_RELAXED);
+                __atomic_store_n(&has_entry[rem.c[e]], (uint8_t)1, __ATOMIC_RELAXED);
+            }
+        });
         std::fill(is_head.begin(), is_head.end(), 0);
         std::fill(placed.begin(), placed.end(), 0);
         std::vector<int32_t> order;
         order.reserve(n);
-        const bool final_level = 2 * (int64_t)ne + n_diag <= 2 * b;
+        const bool final_level = 2 * ne + n_diag <= 2 * b;
         if (final_level) {
             for (int32_t v : greedy_cover(n, eu, ev)) {
                 order.push_back(v);
@@ -341,10 +597,12 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
             }
         } else {
             std::vector<int64_t> deg(n, 0);
-            for (size_t e = 0; e < ne; ++e) {
-                ++deg[eu[e]];
-                ++deg[ev[e]];
-            }
+            par_for(nt, ne, [&](int64_t lo, int64_t hi, int) {
+                for (int64_t e = lo; e < hi; ++e) {
+                    __atomic_fetch_add(&deg[eu[e]], (int64_t)1, __ATOMIC_RELAXED);
+                    __atomic_fetch_add(&deg[ev[e]], (int64_t)1, __ATOMIC_RELAXED);
+                }
+            });
             std::vector<int32_t> cand;
             for (int64_t v = 0; v < n; ++v)
                 if (deg[v] > 0) cand.push_back((int32_t)v);
@@ -361,27 +619,28 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
                 is_head[v] = placed[v] = 1;
             }
             if (opts.la == ARROW_LA_RANDOM_FOREST) {
-                // weights of the edges of G_i - H_i, Kruskal in (key, u, v) order
-                std::vector<uint64_t> wkey;
-                std::vector<uint32_t> widx;
+                // weights of the edges of G_i - H_i (a bijection of the edge id,
+                // so all distinct), then the unique minimum spanning forest
                 const uint64_t ls = sm_output(opts.seed, (uint64_t)level);
-                for (size_t e = 0; e < ne; ++e) {
-                    if (is_head[eu[e]] || is_head[ev[e]]) continue;
-                    wkey.push_back(sm_output(ls, (uint64_t)eu[e] * (uint64_t)n + (uint64_t)ev[e]));
-                    widx.push_back((uint32_t)e);
-                }
-                radix_sort(wkey, widx, 64);  // stable: equal keys keep (u, v) order
-                UnionFind uf(n);
-                std::vector<int32_t> fu, fv;
-                for (size_t j = 0; j < widx.size(); ++j) {
-                    int32_t a = eu[widx[j]], c = ev[widx[j]];
-                    int32_t ra = uf.find(a), rc = uf.find(c);
-                    if (ra != rc) {
-                        uf.parent[std::max(ra, rc)] = std::min(ra, rc);
-                        fu.push_back(a);
-                        fv.push_back(c);
+                std::vector<uint64_t> key(ne);
+                par_for(nt, ne, [&](int64_t lo, int64_t hi, int t) {
+                    int64_t c = 0;
+                    for (int64_t e = lo; e < hi; ++e) {
+                        key[e] = sm_output(ls, (uint64_t)eu[e] * (uint64_t)n + (uint64_t)ev[e]);
+                        c += !is_head[eu[e]] && !is_head[ev[e]];
                     }
-                }
+                    tcnt[t] = c;
+                });
+                std::vector<int64_t> off(tcnt.begin(), tcnt.end());
+                const int64_t nl = exclusive_scan(off);
+                std::vector<int64_t> live(nl);
+                par_for(nt, ne, [&](int64_t lo, int64_t hi, int t) {
+                    int64_t o = off[t];
+                    for (int64_t e = lo; e < hi; ++e)
+                        if (!is_head[eu[e]] && !is_head[ev[e]]) live[o++] = e;
+                });
+                std::vector<int32_t> fu, fv;
+                boruvka_msf(nt, n, eu, ev, key, std::move(live), fu, fv);
                 layout_forest(n, fu, fv, order, placed);
             }
         }
@@ -396,66 +655,114 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
             set_error("internal: arrangement is not a permutation");
             return ARROW_ERR_INTERNAL;
         }
-        for (int64_t p = 0; p < n; ++p) pos[order[p]] = (int32_t)p;
+        par_for(nt, n, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t p = lo; p < hi; ++p) pos[order[p]] = (int32_t)p;
+        });
 
-        // classify the remaining entries
-        Level L;
-        std::vector<int32_t> kp, kq;
-        std::vector<float> kv;
-        Entries next;
-        int64_t maxpos = -1;
-        for (size_t e = 0; e < m; ++e) {
-            int64_t p = pos[rem.r[e]], q = pos[rem.c[e]];
-            bool keep = p < b || q < b || (p > q ? p - q : q - p) <= b;
-            if (keep) {
-                kp.push_back((int32_t)p);
-                kq.push_back((int32_t)q);
-                kv.push_back(rem.v[e]);
-                maxpos = std::max(maxpos, std::max(p, q));
-            } else {
-                next.r.push_back(rem.r[e]);
-                next.c.push_back(rem.c[e]);
-                next.v.push_back(rem.v[e]);
+        auto keep_of = [&](int64_t e, int64_t &p, int64_t &q) {
+            p = pos[rem.r[e]];
+            q = pos[rem.c[e]];
+            return p < b || q < b || (p > q ? p - q : q - p) <= b;
+        };
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+            int64_t c = 0, mx = -1;
+            for (int64_t e = lo; e < hi; ++e) {
+                int64_t p, q;
+                if (keep_of(e, p, q)) {
+                    ++c;
+                    mx = std::max(mx, std::max(p, q));
+                }
             }
-        }
+            tcnt[t] = c;
+            tmax[t] = mx;
+        });
+        for (int t = 0; t < nt; ++t) tcnt2[t] = 0;
+        int64_t maxpos = -1;
+        for (int t = 0; t < nt; ++t) maxpos = std::max(maxpos, tmax[t]);
+        std::vector<int64_t> koff(tcnt.begin(), tcnt.end());
+        const int64_t nk = exclusive_scan(koff);
+        Entries next;
+        next.r.resize(m - nk);
+        next.c.resize(m - nk);
+        next.v.resize(m - nk);
+        std::vector<int32_t> kp(nk), kq(nk);
+        std::vector<float> kv(nk);
+        par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+            int64_t o = koff[t], o2 = lo - koff[t];
+            for (int64_t e = lo; e < hi; ++e) {
+                int64_t p, q;
+                if (keep_of(e, p, q)) {
+                    kp[o] = (int32_t)p;
+                    kq[o] = (int32_t)q;
+                    kv[o] = rem.v[e];
+                    ++o;
+                } else {
+                    next.r[o2] = rem.r[e];
+                    next.c[o2] = rem.c[e];
+                    next.v[o2] = rem.v[e];
+                    ++o2;
+                }
+            }
+        });
         if (final_level && !next.r.empty()) {
             set_error("internal: last level left entries");
             return ARROW_ERR_INTERNAL;
         }
+        Level L;
         L.n_i = level == 0 ? n : maxpos + 1;
         L.vop.assign(order.begin(), order.begin() + L.n_i);
         L.row_ptr.assign(L.n_i + 1, 0);
-        for (int32_t p : kp) ++L.row_ptr[p + 1];
+        par_for(nt, nk, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t e = lo; e < hi; ++e)
+                __atomic_fetch_add(&L.row_ptr[kp[e] + 1], (int64_t)1, __ATOMIC_RELAXED);
+        });
         for (int64_t i = 0; i < L.n_i; ++i) L.row_ptr[i + 1] += L.row_ptr[i];
-        const size_t nk = kp.size();
         L.col.resize(nk);
         L.val.resize(nk);
         {
+            // scatter by row (any order within a row), then sort each row by
+            // column: positions within a row are distinct, so the order is unique
             std::vector<int64_t> fill(L.row_ptr.begin(), L.row_ptr.end() - 1);
-            for (size_t e = 0; e < nk; ++e) {
-                int64_t d = fill[kp[e]]++;
-                L.col[d] = kq[e];
-                L.val[d] = kv[e];
-            }
+            par_for(nt, nk, [&](int64_t lo, int64_t hi, int) {
+                for (int64_t e = lo; e < hi; ++e) {
+                    const int64_t d = __atomic_fetch_add(&fill[kp[e]], (int64_t)1, __ATOMIC_RELAXED);
+                    L.col[d] = kq[e];
+                    L.val[d] = kv[e];
+                }
+            });
         }
-        std::vector<std::pair<int32_t, float>> tmp;
-        for (int64_t i = 0; i < L.n_i; ++i) {
-            int64_t s = L.row_ptr[i], t = L.row_ptr[i + 1];
-            bool sorted = true;
-            for (int64_t j = s + 1; j < t; ++j)
-                if (L.col[j] < L.col[j - 1]) { sorted = false; break; }
-            if (sorted) continue;
-            tmp.clear();
-            for (int64_t j = s; j < t; ++j) tmp.push_back({L.col[j], L.val[j]});
-            std::sort(tmp.begin(), tmp.end(),
-                      [](const std::pair<int32_t, float> &a, const std::pair<int32_t, float> &b) {
-                          return a.first < b.first;
-                      });
-            for (int64_t j = s; j < t; ++j) {
-                L.col[j] = tmp[j - s].first;
-                L.val[j] = tmp[j - s].second;
+        // rows split into ranges of equal entry counts (head rows are long)
+        std::vector<int64_t> rcut(nt + 1, 0);
+        for (int t = 1; t < nt; ++t)
+            rcut[t] = std::max<int64_t>(
+                rcut[t - 1], std::lower_bound(L.row_ptr.begin(), L.row_ptr.end() - 1,
+                                              nk * t / nt) - L.row_ptr.begin());
+        rcut[nt] = L.n_i;
+        par_each(nt, [&](int tt) {
+          {
+            const int64_t lo = rcut[tt], hi = rcut[tt + 1];
+            std::vector<std::pair<int32_t, float>> tmp;
+            for (int64_t i = lo; i < hi; ++i) {
+                const int64_t s = L.row_ptr[i], t = L.row_ptr[i + 1];
+                bool sorted = true;
+                for (int64_t j = s + 1; j < t; ++j)
+                    if (L.col[j] < L.col[j - 1]) {
+                        sorted = false;
+                        break;
+                    }
+                if (sorted) continue;
+                tmp.clear();
+                for (int64_t j = s; j < t; ++j) tmp.push_back({L.col[j], L.val[j]});
+                std::sort(tmp.begin(), tmp.end(),
+                          [](const std::pair<int32_t, float> &a,
+                             const std::pair<int32_t, float> &c) { return a.first < c.first; });
+                for (int64_t j = s; j < t; ++j) {
+                    L.col[j] = tmp[j - s].first;
+                    L.val[j] = tmp[j - s].second;
+                }
             }
-        }
+          }
+        });
         out.levels.push_back(std::move(L));
         rem = std::move(next);
         if (rem.size() == 0) break;

@@ -3,7 +3,7 @@
 // The decomposition's levels become three row passes in level-0 order:
 //  * chunk pass: every row longer than kLongRow, cut into chunks of kChunk
 //    entries (the hub rows behind the load imbalance discussed in Section
-//    6.2; most of them are head rows of B_0, the row tiles of Section 3.1);
+//    7.3; most of them are head rows of B_0, the row tiles of Section 4.1);
 //  * upper pass: the rows of B_i (i >= 1) not folded into level 0, with
 //    columns mapped to level-0 positions through sigma_i = pi_0 o pi_i^{-1};
 //  * level-0 pass: per row, the entries of B_0 and of the short rows of
@@ -32,15 +32,31 @@ namespace {
         }                                                                          \
     } while (0)
 
+Allocator g_allocator;
+
 template <class T>
 arrow_status_t upload(Plan &p, T *&dst, const std::vector<T> &src, hipStream_t s) {
     dst = nullptr;
     if (src.empty()) return ARROW_OK;
     void *d = nullptr;
-    hipError_t e = hipMalloc(&d, src.size() * sizeof(T));
-    if (e != hipSuccess) {
-        set_error(std::string("hipMalloc of plan array: ") + hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? ARROW_ERR_OUT_OF_MEMORY : ARROW_ERR_HIP;
+    const size_t bytes = src.size() * sizeof(T);
+    if (p.allocator.alloc) {
+        d = p.allocator.alloc(bytes, s, p.allocator.ctx);
+        if (!d) {
+            set_error("the plan allocator returned NULL for " + std::to_string(bytes) + " bytes");
+            return ARROW_ERR_OUT_OF_MEMORY;
+        }
+        if (reinterpret_cast<uintptr_t>(d) % 256 != 0) {
+            p.allocator.free(d, nullptr, p.allocator.ctx);
+            set_error("the plan allocator returned a pointer that is not 256-byte aligned");
+            return ARROW_ERR_INVALID_ARG;
+        }
+    } else {
+        hipError_t e = hipMalloc(&d, bytes);
+        if (e != hipSuccess) {
+            set_error(std::string("hipMalloc of plan array: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? ARROW_ERR_OUT_OF_MEMORY : ARROW_ERR_HIP;
+        }
     }
     p.allocs.push_back(d);
     p.footprint += (int64_t)(src.size() * sizeof(T));
@@ -58,6 +74,9 @@ int64_t count_true(const std::vector<uint8_t> &m) {
 }
 
 }  // namespace
+
+Allocator current_allocator() { return g_allocator; }
+void set_allocator(const Allocator &a) { g_allocator = a; }
 
 int64_t elem_size(int dtype) { return dtype == kF32 ? 4 : (dtype == kF8E4M3 ? 1 : 2); }
 
@@ -120,6 +139,7 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     }
     Plan &p = *pp;
     p.device = device;
+    p.allocator = g_allocator;
     p.n = d.n;
     p.nnz = d.nnz;
     p.b = d.b;
@@ -505,7 +525,12 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
 void plan_destroy(Plan *p) {
     if (!p) return;
     hipSetDevice(p->device);
-    for (void *a : p->allocs) hipFree(a);
+    for (void *a : p->allocs) {
+        if (p->allocator.free)
+            p->allocator.free(a, nullptr, p->allocator.ctx);
+        else
+            hipFree(a);
+    }
     for (const ProfRec &r : p->prof_recs) {
         hipEventDestroy(r.start);
         hipEventDestroy(r.stop);

@@ -26,8 +26,19 @@ struct ProfRec {
     hipStream_t stream;
 };
 
+// Device allocator of plan buffers (arrow_set_allocator); null functions =
+// hipMalloc / hipFree.
+struct Allocator {
+    arrow_alloc_fn alloc = nullptr;
+    arrow_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+Allocator current_allocator();
+void set_allocator(const Allocator &a);
+
 struct Plan {
     int device = 0;
+    Allocator allocator;  // the allocator the plan's buffers came from
     int64_t n = 0, nnz = 0;
     int32_t b = 0, levels = 0;
     double a_inf = 0.0;

@@ -1,14 +1,20 @@
 """GPU parity at the benchmark's full sizes, in the launch sequence bench.py
-times: permute_in, T chained products over all k columns through arrow_spmm
+times: permute_in, T chained products through arrow_spmm over all k columns
 (1/nu of step t-1 folded into step t, two ping-pong buffers), permute_out with
-the last 1/nu.  The oracle follows sampled columns only: the iteration is
-column-separable (each column is normalised on its own), so the FP64 CSR
-iteration of a few columns of X_0 at full n is the exact reference for them.
+the last 1/nu.  The products are Y_t = A X_t with X_{t+1} = Y_t / ||Y_t||_col
+(the iteration of Section 2, "Matrices", over the decomposition of Section 4,
+Eq. (1)).
 
-Gates: FP32 -- X_T and every nu_t within 1e-5 (relative) on the sampled
-columns.  BF16 / FP8 -- the first product, teacher-forced from the stored
-X_0, within the per-step bound on the sampled columns; the drift of X_T after
-T steps against the FP64 trajectory is reported.
+FP32 (every column, every iteration, relative Frobenius error over n x k):
+  teacher-forced  -- Y_t against one FP64 oracle product of exactly the X_t the
+                     GPU consumed (the stored Y_{t-1} / nu_{t-1}) <= 1e-5;
+  free-running    -- Y_t against the oracle's own FP64 trajectory from X_0
+                     <= 1e-5; every nu_t within 1e-5; X_T after permute_out.
+  The worst column's relative error is reported beside each.
+BF16 / FP16 / FP8: teacher-forced steps t = 0, T/2 and T-1 on every column
+  within the format's per-step bound; the drift of the free-running X_T from
+  the FP64 trajectory is reported on sampled columns (the iteration is
+  column-separable: each column is normalised on its own).
 """
 import time
 
@@ -39,8 +45,9 @@ def _gpu():
 
 
 def _plan(name):
-    """Matrix, decomposition and plan of a workload (cached per module)."""
+    """Matrix, decomposition and plan of a workload (one resident at a time)."""
     if name not in _CACHE:
+        _CACHE.clear()
         w = W.WORKLOADS[name]
         t0 = time.perf_counter()
         M = W.workload_matrix(w)
@@ -50,116 +57,170 @@ def _plan(name):
         plan = A_.Plan(d)
         vop0 = d.level(0)["vop"].astype(np.int64)
         say(f"[full] {name}: {d.info()['levels']} levels, plan in {time.perf_counter() - t0:.1f}s")
-        _CACHE.clear()  # one full-size plan resident at a time
         _CACHE[name] = (w, M, plan, vop0)
     return _CACHE[name]
+
+
+def _to_orig(v_plan, vop0):
+    out = np.empty_like(v_plan)
+    out[vop0] = v_plan
+    return out
+
+
+_TABLES = {}
+
+
+def _decode(y, dtype):
+    """Stored codes of a plan-order buffer as float64: the oracle's format
+    definitions, applied through a table of every code."""
+    if dtype == "f32":
+        return y.cpu().numpy().astype(np.float64)
+    if dtype not in _TABLES:
+        ncodes = 256 if dtype == "f8e4m3" else 65536
+        _TABLES[dtype] = Q.decode(np.arange(ncodes, dtype=np.int64), dtype)
+    if dtype in ("bf16", "f16"):
+        codes = y.view(torch.int16).cpu().numpy().view(np.uint16)
+    else:
+        codes = y.view(torch.uint8).cpu().numpy()
+    return _TABLES[dtype][codes]
+
+
+def _col_errors(a, ref):
+    """Relative 2-norm error of every column (0/0 -> 0)."""
+    num = np.sqrt(np.sum((a - ref) ** 2, axis=0))
+    den = np.sqrt(np.sum(ref * ref, axis=0))
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
+
+
+class _Run:
+    """bench.py's launch sequence, one product at a time; `hook(t, y, state)`
+    sees every stored Y_t (plan order) with its scale and 1/nu."""
+
+    def __init__(self, plan, X0, dtype):
+        n, k = X0.shape
+        self.plan, self.dtype, self.k = plan, dtype, k
+        dev = "cuda"
+        self.scaled = dtype in ("f16", "f8e4m3")
+        self.x = torch.from_numpy(X0).to(dev)
+        self.xp = plan.empty(k, dtype)
+        self.xs = torch.ones(k, dtype=torch.float32, device=dev)
+        self.xm = torch.zeros(k, dtype=torch.float32, device=dev)
+        self.bufs = [plan.empty(k, dtype), plan.empty(k, dtype)]
+        self.inv = [torch.zeros(k, dtype=torch.float64, device=dev) for _ in range(2)]
+        self.scl = [torch.ones(k, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.mx = [torch.zeros(k, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.ws = plan.workspace(plan.workspace_size(k, dtype))
+
+    def run(self, T, hook):
+        plan, dtype, s = self.plan, self.dtype, self.scaled
+        plan.permute_in(self.x, self.xp, dtype, x_scale=self.xs if s else None,
+                        x_maxabs=self.xm if s else None)
+        norms = torch.zeros((T, self.k), dtype=torch.float64, device="cuda")
+        cur, cur_s, cur_m = self.xp, (self.xs if s else None), (self.xm if s else None)
+        for t in range(T):
+            y = self.bufs[t % 2]
+            op = A_.operand(cur, y, dtype, x_scale=cur_s,
+                            x_inv_norm=self.inv[(t - 1) % 2] if t > 0 else None,
+                            x_maxabs=cur_m, y_scale=self.scl[t % 2] if s else None,
+                            y_maxabs=self.mx[t % 2] if s else None,
+                            y_norm=norms[t], y_inv_norm=self.inv[t % 2])
+            plan.spmm([op], self.ws)
+            if hook is not None:
+                torch.cuda.synchronize()
+                hook(t, y, self.scl[t % 2] if s else None, self.inv[t % 2], norms[t])
+            cur, cur_s, cur_m = y, (self.scl[t % 2] if s else None), \
+                (self.mx[t % 2] if s else None)
+        out = torch.empty((self.x.shape[0], self.k), dtype=torch.float32, device="cuda")
+        plan.permute_out(cur, out, dtype, x_scale=cur_s, col_factor=self.inv[(T - 1) % 2])
+        torch.cuda.synchronize()
+        return out, norms
+
+
+@pytest.mark.parametrize("name", ["grid2048", "rmat22"])
+def test_full_size_fp32_every_column_every_iteration(name):
+    w, M, plan, vop0 = _plan(name)
+    T, k = w.iters, w.k
+    X0 = W.features(M.n, k, w.seeds["x"])
+    st = {"x_gpu": X0.astype(np.float64), "x_ref": X0.astype(np.float64),
+          "tf": [], "fr": [], "col": [], "nu": []}
+    t_oracle = [0.0]
+
+    def hook(t, y, scale, inv, nrm):
+        y_t = _to_orig(_decode(y, "f32"), vop0)
+        nu = nrm.cpu().numpy()
+        t0 = time.perf_counter()
+        tf_ref = S.csr_spmm(M, st["x_gpu"])          # one step from the GPU's own input
+        fr_ref = S.csr_spmm(M, st["x_ref"])          # the oracle's own trajectory
+        nu_ref, x_next = S.renormalize(fr_ref)
+        t_oracle[0] += time.perf_counter() - t0
+        tf, fr = S.rel_fro(y_t, tf_ref), S.rel_fro(y_t, fr_ref)
+        col = max(float(_col_errors(y_t, tf_ref).max()), float(_col_errors(y_t, fr_ref).max()))
+        nerr = float(np.max(np.abs(nu - nu_ref) / nu_ref))
+        st["tf"].append(tf), st["fr"].append(fr), st["col"].append(col), st["nu"].append(nerr)
+        say(f"[full] {name} f32 t={t}: teacher-forced {tf:.2e}, free-running {fr:.2e}, "
+            f"worst column {col:.2e}, norm {nerr:.2e}")
+        inv_h = inv.cpu().numpy()
+        st["x_gpu"] = y_t * inv_h[None, :]
+        st["x_ref"] = x_next
+        assert tf <= TOL and fr <= TOL and nerr <= TOL, (t, tf, fr, nerr)
+
+    out, norms = _Run(plan, X0, "f32").run(T, hook)
+    xt = out.cpu().numpy().astype(np.float64)
+    err_xt = S.rel_fro(xt, st["x_ref"])
+    say(f"[full] {name} f32 k={k} T={T}: worst teacher-forced {max(st['tf']):.2e}, worst "
+        f"free-running {max(st['fr']):.2e}, worst column {max(st['col']):.2e}, worst norm "
+        f"{max(st['nu']):.2e}, X_T {err_xt:.2e} (oracle {t_oracle[0]:.1f}s, "
+        f"{S.num_threads()} threads)")
+    assert len(st["tf"]) == T
+    assert err_xt <= TOL
 
 
 def _sample_cols(k):
     return sorted({0, k // 3, (2 * k) // 3, k - 1})
 
 
-def _run(plan, X0, dtype, T, cols):
-    """bench.py's launch sequence; returns the sampled columns of X_T (FP32,
-    original order), the per-step norms [T, k] and the stored first product
-    with its scale."""
-    n, k = X0.shape
-    dev = "cuda"
-    scaled = dtype in ("f16", "f8e4m3")
-    x = torch.from_numpy(X0).to(dev)
-    xp = plan.empty(k, dtype)
-    xs = torch.ones(k, dtype=torch.float32, device=dev)
-    xm = torch.zeros(k, dtype=torch.float32, device=dev)
-    plan.permute_in(x, xp, dtype, x_scale=xs if scaled else None, x_maxabs=xm if scaled else None)
-    bufs = [plan.empty(k, dtype), plan.empty(k, dtype)]
-    inv = [torch.zeros(k, dtype=torch.float64, device=dev) for _ in range(2)]
-    scl = [torch.ones(k, dtype=torch.float32, device=dev) for _ in range(2)]
-    mx = [torch.zeros(k, dtype=torch.float32, device=dev) for _ in range(2)]
-    norms = torch.zeros((T, k), dtype=torch.float64, device=dev)
-    ws = plan.workspace(plan.workspace_size(k, dtype))
-    cur, cur_s, cur_m = xp, (xs if scaled else None), (xm if scaled else None)
-    first = None
-    for t in range(T):
-        y = bufs[t % 2]
-        op = A_.operand(cur, y, dtype, x_scale=cur_s,
-                        x_inv_norm=inv[(t - 1) % 2] if t > 0 else None,
-                        x_maxabs=cur_m,
-                        y_scale=scl[t % 2] if scaled else None,
-                        y_maxabs=mx[t % 2] if scaled else None,
-                        y_norm=norms[t], y_inv_norm=inv[t % 2])
-        plan.spmm([op], ws)
-        if t == 0:
-            torch.cuda.synchronize()
-            first = (y.clone(), scl[0].clone() if scaled else None)
-        cur, cur_s, cur_m = y, (scl[t % 2] if scaled else None), (mx[t % 2] if scaled else None)
-    out = torch.empty((n, k), dtype=torch.float32, device=dev)
-    plan.permute_out(cur, out, dtype, x_scale=cur_s, col_factor=inv[(T - 1) % 2])
-    torch.cuda.synchronize()
-    xs_host = xs.cpu().numpy().astype(np.float64) if scaled else None
-    xt = out[:, cols].cpu().numpy().astype(np.float64)
-    return xt, norms.cpu().numpy(), first, xp, xs_host
+@pytest.mark.parametrize("name,dtype", [("grid3d160", "bf16"), ("grid3d160", "f16"),
+                                        ("grid3d160", "f8e4m3"), ("rmat22_k128", "bf16"),
+                                        ("rmat22_k128", "f16"), ("rmat22_k128", "f8e4m3")])
+def test_full_size_precision_teacher_forced(name, dtype):
+    w, M, plan, vop0 = _plan(name)
+    T, k = w.iters, w.k
+    X0 = W.features(M.n, k, w.seeds["x"])
+    gated = (0, T // 2, T - 1)
+    keep = set(gated) | {t - 1 for t in gated if t > 0}
+    stored = {}
 
+    def hook(t, y, scale, inv, nrm):
+        if t in keep:
+            v = _decode(y, dtype)
+            if scale is not None:
+                v = v * scale.cpu().numpy().astype(np.float64)[None, :]
+            stored[t] = (_to_orig(v, vop0), inv.cpu().numpy())
 
-def _oracle(M, X0c, T):
-    """FP64 trajectory of the sampled columns: X_T and the norms of every step."""
-    X = X0c.astype(np.float64)
-    nus = []
+    run = _Run(plan, X0, dtype)
+    out, norms = run.run(T, hook)
+    # the stored X_0 (permute_in's codes and scales)
+    x0 = _decode(run.xp, dtype)
+    if run.scaled:
+        x0 = x0 * run.xs.cpu().numpy().astype(np.float64)[None, :]
+    x0 = _to_orig(x0, vop0)
+    worst = 0.0
+    for t in gated:
+        x_in = x0 if t == 0 else stored[t - 1][0] * stored[t - 1][1][None, :]
+        ref = S.csr_spmm(M, x_in)
+        err = S.rel_fro(stored[t][0], ref)
+        col = float(_col_errors(stored[t][0], ref).max())
+        say(f"[full] {name} {dtype} t={t}: teacher-forced {err:.2e} (bound "
+            f"{Q.STEP_BOUND[dtype]:g}), worst column {col:.2e}")
+        assert err <= Q.STEP_BOUND[dtype], (t, err)
+        worst = max(worst, err)
+    # drift of the free-running X_T against the FP64 trajectory (reported)
+    cols = _sample_cols(k)
+    X = X0[:, cols].astype(np.float64)
     for _ in range(T):
-        nu, X = S.renormalize(S.csr_spmm(M, X))
-        nus.append(nu)
-    return X, np.array(nus)
-
-
-def _decoded_plan_to_orig(y, dtype, scale, vop0, cols):
-    """Stored plan-order values of the sampled columns, decoded (oracle format
-    definitions), in the original order."""
-    if dtype == "f32":
-        v = y[:, cols].cpu().numpy().astype(np.float64)
-    elif dtype in ("bf16", "f16"):
-        v = Q.decode(y.view(torch.int16)[:, cols].cpu().numpy().view(np.uint16), dtype)
-    else:
-        v = Q.decode(y.view(torch.uint8)[:, cols].cpu().numpy(), "f8e4m3")
-    if scale is not None:
-        v = v * np.asarray(scale, np.float64)[cols][None, :]
-    out = np.empty_like(v)
-    out[vop0] = v
-    return out
-
-
-@pytest.mark.parametrize("name", ["grid2048", "rmat22"])
-def test_full_size_fp32(name):
-    w, M, plan, vop0 = _plan(name)
-    X0 = W.features(M.n, w.k, w.seeds["x"])
-    cols = _sample_cols(w.k)
-    XT, norms, _, _, _ = _run(plan, X0, "f32", w.iters, cols)
-    t0 = time.perf_counter()
-    ref_X, ref_nu = _oracle(M, X0[:, cols], w.iters)
-    err = S.rel_fro(XT, ref_X)
-    nerr = float(np.max(np.abs(norms[:, cols] - ref_nu) / ref_nu))
-    say(f"[full] {name} f32 k={w.k} T={w.iters}: X_T error {err:.2e}, worst norm error "
-        f"{nerr:.2e} on columns {cols} (oracle {time.perf_counter() - t0:.1f}s)")
-    assert err <= TOL
-    assert nerr <= TOL
-
-
-@pytest.mark.parametrize("name,dtype", [("grid3d160", "bf16"), ("grid3d160", "f8e4m3"),
-                                        ("rmat22_k128", "bf16"), ("rmat22_k128", "f8e4m3")])
-def test_full_size_precision(name, dtype):
-    w, M, plan, vop0 = _plan(name)
-    X0 = W.features(M.n, w.k, w.seeds["x"])
-    cols = _sample_cols(w.k)
-    XT, norms, (y0, s0), xp, xs = _run(plan, X0, dtype, w.iters, cols)
-    # first product, teacher forced from the stored X_0 of the sampled columns
-    x0_dec = _decoded_plan_to_orig(xp, dtype, xs, vop0, cols)
-    y0_dec = _decoded_plan_to_orig(y0, dtype, None if s0 is None else s0.cpu().numpy(), vop0,
-                                   cols)
-    ref0 = S.csr_spmm(M, x0_dec)
-    step = S.rel_fro(y0_dec, ref0)
-    # drift of the free-running trajectory after T steps
-    ref_X, _ = _oracle(M, X0[:, cols], w.iters)
-    drift = S.rel_fro(XT, ref_X)
-    say(f"[full] {name} {dtype} k={w.k} T={w.iters}: first-step error {step:.2e} "
-        f"(bound {Q.STEP_BOUND[dtype]:g}), drift after {w.iters} steps {drift:.2e} "
-        f"(reported) on columns {cols}")
-    assert step <= Q.STEP_BOUND[dtype]
-    assert np.all(np.isfinite(XT)) and np.all(norms[:, cols] > 0)
+        _, X = S.renormalize(S.csr_spmm(M, X))
+    xt = out[:, cols].cpu().numpy().astype(np.float64)
+    drift = S.rel_fro(xt, X)
+    say(f"[full] {name} {dtype} k={k} T={T}: worst teacher-forced {worst:.2e}, drift after "
+        f"{T} steps {drift:.2e} (reported, columns {cols})")
+    assert np.all(np.isfinite(out.cpu().numpy())) and bool(torch.all(norms > 0))

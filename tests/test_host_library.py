@@ -1,6 +1,7 @@
 """Host side of libarrow on the CPU: decomposition parity with the oracle's
 LA-Decompose (bit-exact: integer / index work), validity at larger sizes,
 save/load, error paths and the exported C-ABI symbols."""
+import ctypes
 import os
 import re
 import subprocess
@@ -189,3 +190,83 @@ def test_exports_every_declared_symbol():
     for name in declared:
         getattr(A_.lib(), name)
     assert A_.version() == "1.0.0"
+
+
+def _fnv1a(data: bytes) -> int:
+    h = 1469598103934665603
+    for c in data:
+        h = ((h ^ c) * 1099511628211) & ((1 << 64) - 1)
+    return h
+
+
+def _rewrite(path, mutate):
+    """Apply mutate(bytearray, layout) to a saved decomposition and restore a
+    valid checksum, so only the structural checks can reject the file."""
+    raw = bytearray(open(path, "rb").read())
+    n = int(np.frombuffer(bytes(raw[16:24]), np.int64)[0])
+    off = 56
+    n_i = int(np.frombuffer(bytes(raw[off:off + 8]), np.int64)[0])
+    nnz_i = int(np.frombuffer(bytes(raw[off + 8:off + 16]), np.int64)[0])
+    vop_off = off + 16
+    rp_off = vop_off + 4 * n_i
+    col_off = rp_off + 8 * (n_i + 1)
+    rp = np.frombuffer(bytes(raw[rp_off:col_off]), np.int64)
+    mutate(raw, dict(n=n, n_i=n_i, nnz_i=nnz_i, vop=vop_off, rp=rp, col=col_off))
+    body = bytes(raw[:-8])
+    raw[-8:] = np.array([_fnv1a(body)], dtype=np.uint64).tobytes()
+    open(path, "wb").write(bytes(raw))
+
+
+def test_load_rejects_structurally_invalid_files(tmp_path):
+    # a path in natural order: level 0 is the path itself (bandwidth 1)
+    A = W.from_edges(10, [(i, i + 1) for i in range(9)])
+    d = _lib_decompose(A, 2, la=A_.LA_IDENTITY)
+    assert d.info()["levels"] == 1
+    p = str(tmp_path / "ok.arrow")
+    d.save(p)
+    _rewrite(p, lambda raw, lay: None)          # checksum recomputed, nothing changed
+    _assert_same(A_.Decomposition.load(p).levels(), d.levels())
+
+    def outside_arrow(raw, lay):                # row 9: column 8 -> 5 (|9 - 5| > b, 5 >= b)
+        e = int(lay["rp"][9])
+        raw[lay["col"] + 4 * e:lay["col"] + 4 * e + 4] = np.int32(5).tobytes()
+
+    def not_injective(raw, lay):                # position 1 holds the vertex of position 0
+        raw[lay["vop"] + 4:lay["vop"] + 8] = raw[lay["vop"]:lay["vop"] + 4]
+
+    def unsorted(raw, lay):                     # row 5 holds columns 4, 6: swap them
+        e = int(lay["rp"][5])
+        a = bytes(raw[lay["col"] + 4 * e:lay["col"] + 4 * e + 4])
+        raw[lay["col"] + 4 * e:lay["col"] + 4 * e + 4] = raw[lay["col"] + 4 * e + 4:
+                                                              lay["col"] + 4 * e + 8]
+        raw[lay["col"] + 4 * e + 4:lay["col"] + 4 * e + 8] = a
+
+    for name, fn, why in (("arrow", outside_arrow, "outside the arrow"),
+                          ("inj", not_injective, "not injective"),
+                          ("sort", unsorted, "not increasing")):
+        q = str(tmp_path / f"{name}.arrow")
+        d.save(q)
+        _rewrite(q, fn)
+        with pytest.raises(A_.ArrowError) as e:
+            A_.Decomposition.load(q)
+        assert e.value.status == A_.ERR_IO, name
+        assert why in A_.lib().arrow_last_error().decode(), name
+
+
+def test_allocator_and_threads_arguments():
+    lib = A_.lib()
+    # both functions or neither
+    assert lib.arrow_set_allocator(None, None, None) == A_.OK
+    cb = A_.ALLOC_FN(lambda n, s, c: None)
+    assert lib.arrow_set_allocator(ctypes.cast(cb, ctypes.c_void_p), None, None) == \
+        A_.ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        A_.set_allocator(lambda n, s: 0, None)
+    A_.set_allocator(None, None)
+    A = W.make_matrix("rmat", 10, "row_normalized", 5, 6, 16)
+    with pytest.raises(A_.ArrowError) as e:
+        A_.Decomposition.from_matrix(A, 16, threads=-1)
+    assert e.value.status == A_.ERR_INVALID_ARG
+    ref = _lib_decompose(A, 16, seed=4).levels()
+    for t in (1, 2, 3, 8):
+        _assert_same(A_.Decomposition.from_matrix(A, 16, seed=4, threads=t).levels(), ref)

@@ -319,7 +319,7 @@ def _random_tree(n, rng, kind):
 @pytest.mark.parametrize("kind", ["random", "caterpillar", "broom", "dary"])
 def test_smallest_first_lemma(kind):
     """Smallest-first order keeps at least min(n-1, ceil((x-1)(n-1)/x)+1) tree
-    edges within an x*Delta band (Section 4.4 lemma)."""
+    edges within an x*Delta band (Section 5.4 lemma)."""
     rng = np.random.default_rng(4)
     for n in (30, 200, 700):
         e = _random_tree(n, rng, kind)

@@ -5,7 +5,7 @@ feature matrices.  It holds none of the method's arithmetic (no products, no
 decomposition, no norms), so that the oracle and the HIP path can both consume
 its output without sharing any computation.
 
-The paper evaluates on large SuiteSparse graphs (Section 6, Table 2).  Those
+The paper evaluates on large SuiteSparse graphs (Section 7, Table 2).  Those
 are not available here; seeded generators with the same structure stand in:
 
 * 2D 5-point and 3D 7-point grids (low degree, small bandwidth in natural
