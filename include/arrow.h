@@ -292,6 +292,24 @@ typedef struct {
 arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t num_ops,
                           void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * arrow_spmm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same products, bit for bit, with the workspace taken from a fixed array of
+ * ARROW_STATIC_WORKSPACE_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  Calls no allocating routine.  Operands are as for
+ * arrow_spmm.  Returns ARROW_ERR_UNSUPPORTED, before any device work, when
+ * the operands need more than ARROW_STATIC_WORKSPACE_BYTES of workspace
+ * (the sum of arrow_workspace_size over the operands).  Every call on one GPU
+ * shares that GPU's array (no part of it needs to start at zero: a call reads
+ * only what it wrote itself), so calls that overlap in time on one GPU -- on
+ * different streams, or from several host threads -- race and give wrong
+ * results; serialise them.
+ */
+#define ARROW_STATIC_WORKSPACE_BYTES (64u << 20)
+arrow_status_t arrow_spmm_static(arrow_plan_t p, const arrow_operand_t *ops, int32_t num_ops,
+                                 void *stream);
+
 /* Workspace for arrow_spmm_iterate (product buffers plus the ping-pong state). */
 arrow_status_t arrow_iterate_workspace_size(arrow_plan_t p, int64_t k, arrow_dtype_t dtype,
                                             size_t *bytes);

@@ -24,6 +24,7 @@ KERNEL_CHUNKS, KERNEL_UPPER, KERNEL_LEVEL0, KERNEL_NORM, KERNEL_PERMUTE = range(
 KERNEL_NAMES = {KERNEL_CHUNKS: "chunks", KERNEL_UPPER: "upper", KERNEL_LEVEL0: "level0",
                 KERNEL_NORM: "norm", KERNEL_PERMUTE: "permute"}
 ITER_RENORM = 1
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 DTYPES = {"f32": F32, "f16": F16, "bf16": BF16, "f8e4m3": F8E4M3}
 ELEM_SIZE = {F32: 4, F16: 2, BF16: 2, F8E4M3: 1}
@@ -66,6 +67,7 @@ def _load():
         "arrow_permute_in": [P, P, I64, P, I64, I32, I64, P, P, P],
         "arrow_permute_out": [P, P, I64, I32, I64, P, P, P, I64, P],
         "arrow_spmm": [P, P, I32, P, SZ, P],
+        "arrow_spmm_static": [P, P, I32, P],
         "arrow_spmm_iterate": [P, P, P, I64, I64, I32, P, P, I32, U32, P, P, SZ, P],
         "arrow_csr_workspace_size": [I64, I64, ctypes.POINTER(SZ)],
         "arrow_csr_batch": [I64, P, ctypes.POINTER(I32)],
@@ -402,6 +404,13 @@ class Plan:
         _check(_load().arrow_spmm(self._h, ctypes.cast(arr, ctypes.c_void_p), len(ops),
                                   _tptr(workspace), workspace.numel() * workspace.element_size(),
                                   _stream_handle(stream)))
+
+    def spmm_static(self, ops: Sequence[Operand], stream=None):
+        """arrow_spmm with the library's fixed per-GPU workspace (allocates
+        nothing; calls that overlap on one GPU race)."""
+        arr = (Operand * len(ops))(*ops)
+        _check(_load().arrow_spmm_static(self._h, ctypes.cast(arr, ctypes.c_void_p), len(ops),
+                                         _stream_handle(stream)))
 
     def iterate(self, x, y, iters: int, dtype="f32", renorm: bool = True, norms=None,
                 x_scale=None, y_scale=None, workspace=None, stream=None):

@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["kernels_f32.hip", "kernels_bf16.hip", "kernels_f16.hip", "kernels_f8e4m3.hip",
-           "kernels.hip", "plan.cpp", "capi.cpp", "decompose.cpp", "decomp_io.cpp",
+           "kernels.hip", "static_ws.hip", "plan.cpp", "capi.cpp", "decompose.cpp", "decomp_io.cpp",
            "baseline_rocsparse.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",

@@ -25,6 +25,8 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 using arrow::set_error;
 
+int arrow::plan_device(arrow_plan_t p) { return p ? p->p->device : -1; }
+
 namespace {
 
 bool valid_dtype(arrow_dtype_t t) { return t >= ARROW_F32 && t <= ARROW_F8E4M3; }

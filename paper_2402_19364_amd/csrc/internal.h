@@ -35,6 +35,9 @@ void set_error(const std::string &msg);
 arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
                          const float *val, const arrow_decompose_opts_t &opts, Decomp &out);
 
+// Device of a plan handle.
+int plan_device(arrow_plan_t p);
+
 arrow_status_t save_decomp(const Decomp &d, const char *path);
 arrow_status_t load_decomp(const char *path, Decomp &out);
 
