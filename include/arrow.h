@@ -283,11 +283,19 @@ typedef struct {
 } arrow_operand_t;
 
 /*
- * One product Y = A X for each operand, enqueued on `stream`.  Column norms
- * are computed in FP64 with a fixed reduction order, so every operand's
- * result is bitwise independent of the other operands in the call.
- * `workspace` (device) must hold arrow_workspace_size bytes per operand
- * (the sum over operands).
+ * One product Y = A X for each operand (Section 4, Eq. (1): every level's
+ * arrow product, the head-row panels and head-column strips of Alg. 1, and
+ * the forward permutation and reverse accumulation of Alg. 2, fused into
+ * row passes in level-0 order), enqueued on `stream`.  Operands of one
+ * storage type and one tile width (the largest of 128, 64, 32, 16 dividing
+ * k) share one launch sequence over all their column tiles, so the matrix is
+ * read once for all of them (requests on the same graph batched into a wider
+ * k).  The work partition depends only on the plan, k and the storage type,
+ * and column norms are reduced in FP64 in a fixed order, so every operand's
+ * result is bitwise the one it gets alone.  No operand's y may overlap
+ * another operand's x or y (ARROW_ERR_INVALID_ARG).  `workspace` (device,
+ * 256-byte aligned) must hold arrow_workspace_size bytes per operand (the
+ * sum over operands, in operand order).
  */
 arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t num_ops,
                           void *workspace, size_t ws_bytes, void *stream);

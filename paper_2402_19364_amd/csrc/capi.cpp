@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "arrow.h"
 #include "internal.h"
@@ -497,19 +498,57 @@ arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t nu
         set_error("workspace too small: need " + std::to_string(need) + " bytes");
         return ARROW_ERR_INVALID_ARG;
     }
+    // the products of one call run together: no operand's output may overlap
+    // another operand's input or output
+    for (int32_t i = 0; i < num_ops && P.n > 0; ++i) {
+        const int64_t esi = arrow::elem_size(ops[i].dtype);
+        const int64_t yb = ((P.n - 1) * ops[i].ldy + ops[i].k) * esi;
+        for (int32_t j = 0; j < num_ops; ++j) {
+            if (j == i) continue;
+            const int64_t esj = arrow::elem_size(ops[j].dtype);
+            if (overlaps(ops[i].y, yb, ops[j].x, ((P.n - 1) * ops[j].ldx + ops[j].k) * esj) ||
+                overlaps(ops[i].y, yb, ops[j].y, ((P.n - 1) * ops[j].ldy + ops[j].k) * esj)) {
+                set_error("operand " + std::to_string(i) + " writes memory that operand " +
+                          std::to_string(j) + " reads or writes");
+                return ARROW_ERR_INVALID_ARG;
+            }
+        }
+    }
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
         set_error("workspace must be 256-byte aligned");
         return ARROW_ERR_INVALID_ARG;
     }
     DeviceGuard g(P.device);
+    // operands of one storage type and tile width share one launch sequence
+    // (the matrix is read once for all of them); each operand's result is the
+    // one it gets alone
+    std::vector<arrow::OpState> st(num_ops);
+    std::vector<void *> ws(num_ops);
     char *w = static_cast<char *>(workspace);
     for (int32_t i = 0; i < num_ops; ++i) {
         const arrow_operand_t &o = ops[i];
-        arrow::OpState st{o.x, o.y, o.k, o.ldx, o.ldy, o.dtype, o.x_scale, o.x_inv_norm,
-                          o.x_maxabs, o.y_scale, o.y_maxabs, o.y_norm, o.y_inv_norm};
-        if (arrow_status_t r = arrow::spmm_one(P, st, w, static_cast<hipStream_t>(stream)))
-            return r;
+        st[i] = arrow::OpState{o.x, o.y, o.k, o.ldx, o.ldy, o.dtype, o.x_scale, o.x_inv_norm,
+                               o.x_maxabs, o.y_scale, o.y_maxabs, o.y_norm, o.y_inv_norm};
+        ws[i] = w;
         w += arrow::op_workspace(P, o.k, o.dtype);
+    }
+    std::vector<uint8_t> done(num_ops, 0);
+    std::vector<arrow::OpState> gops;
+    std::vector<void *> gws;
+    for (int32_t i = 0; i < num_ops; ++i) {
+        if (done[i]) continue;
+        gops.clear();
+        gws.clear();
+        for (int32_t j = i; j < num_ops; ++j)
+            if (!done[j] && st[j].dtype == st[i].dtype &&
+                arrow::tile_width(st[j].k) == arrow::tile_width(st[i].k)) {
+                gops.push_back(st[j]);
+                gws.push_back(ws[j]);
+                done[j] = 1;
+            }
+        if (arrow_status_t r = arrow::spmm_group(P, gops.data(), (int)gops.size(), gws.data(),
+                                                 static_cast<hipStream_t>(stream)))
+            return r;
     }
     return ARROW_OK;
 }

@@ -74,6 +74,14 @@ struct Tile {
     float a_inf;
 };
 
+// Column tiles of the operands of one launch (same storage type and tile
+// width), run one after the other by every workgroup.
+constexpr int kMaxTiles = 8;
+struct TileSet {
+    Tile t[kMaxTiles];
+    int32_t n;
+};
+
 struct NormArgs {
     const double *part_sumsq;
     const float *part_max;
@@ -84,7 +92,7 @@ struct NormArgs {
 };
 
 hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
-                           const Tile &t, hipStream_t s);
+                           const TileSet &t, hipStream_t s);
 hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t count, hipStream_t s);
 hipError_t launch_colmax(const float *x, int64_t ldx, int64_t n, int k, unsigned *out,

@@ -119,7 +119,7 @@ ARROW_DECLARE_DT(kF8E4M3)
 
 
 hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
-                           const Tile &t, hipStream_t s) {
+                           const TileSet &t, hipStream_t s) {
     switch (dtype) {
     case kF32: return row_pass_dt<kF32>(kt, mode, code16, rp, t, s);
     case kF16: return row_pass_dt<kF16>(kt, mode, code16, rp, t, s);

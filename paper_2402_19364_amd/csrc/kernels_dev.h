@@ -233,10 +233,17 @@ template <int DT, bool CONTRIB, bool FINAL, int BATCH>
 constexpr int row_waves_hint() {
     return DT == kF32 && FINAL && !CONTRIB && BATCH != kBatchWide && BATCH <= 5 ? 7 : 1;
 }
+// A launch covers the column tiles of several operands (same storage type
+// and tile width): workgroup i takes tile i % n of block i / n, so the n
+// workgroups of one block run next to each other and the block's matrix
+// entries come from HBM once for all operands (requests on one graph batched
+// into a wider k).  Each tile sees the workgroup partition and the sums of a
+// launch with that tile alone.
 template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((
     amdgpu_waves_per_eu(row_waves_hint<DT, CONTRIB, FINAL, BATCH>()))) void row_kernel(RowPass rp,
-                                                                                         Tile t) {
+                                                                                         TileSet ts) {
+    const Tile &t = ts.t[blockIdx.x % ts.n];
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;             // lanes per row
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     __shared__ int32_t s_fcol[FAR ? kStageEntries : 1];
     __shared__ int32_t s_fb[2];
 
-    const int wg = row_block(blockIdx.x);
+    const int wg = row_block(blockIdx.x / ts.n);
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave = tid / kWave;
@@ -638,7 +645,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
 // by a fixed butterfly over the group bits and group 0 writes the FP32
 // partial row.  A workgroup handles rows_per_block consecutive chunks.
 template <int KT, int DT, bool OFF32>
-__global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, Tile t) {
+__global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, TileSet ts) {
+    const Tile &t = ts.t[blockIdx.x % ts.n];
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;
@@ -647,7 +655,7 @@ __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, Tile t
     constexpr int UNR = PER < 8 ? PER : 8;
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
-    const int wg = row_block(blockIdx.x);
+    const int wg = row_block(blockIdx.x / ts.n);
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const int g = lane / LPR;
@@ -701,6 +709,7 @@ __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, Tile t
         }
     }
 }
+
 
 
 // ---------------------------------------------------------------------------
@@ -814,9 +823,9 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
 namespace detail {
 
 template <int KT, int DT, bool OFF32, int BATCH>
-hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const Tile &t,
+hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const TileSet &t,
                         hipStream_t s) {
-    dim3 grid(rp.nwg), block(dev::kBlockThreads);
+    dim3 grid((unsigned)((int64_t)rp.nwg * t.n)), block(dev::kBlockThreads);
     switch (mode) {
     case kPassChunk:
         hipLaunchKernelGGL((dev::chunk_kernel<KT, DT, OFF32>), grid, block, 0, s, rp, t);
@@ -865,7 +874,7 @@ hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const Tile &t,
 // Short batches are built for 32-bit offsets only (X and the partial-row
 // buffer below 4 GiB); larger operands take the wide batch.
 template <int KT, int DT, bool OFF32>
-hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
+hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const TileSet &t,
                         hipStream_t s) {
     if (rp.nwg <= 0) return hipSuccess;
     if constexpr (OFF32) {
@@ -884,14 +893,16 @@ hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const Tile &t,
 }
 
 template <int KT, int DT>
-hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const Tile &t, hipStream_t s) {
-    if (t.x_span < (int64_t(1) << 32) && t.s_span < (int64_t(1) << 32))
-        return launch_row_o<KT, DT, true>(mode, code16, rp, t, s);
+hipError_t launch_row_t(int mode, bool code16, const RowPass &rp, const TileSet &t, hipStream_t s) {
+    bool off32 = true;
+    for (int i = 0; i < t.n; ++i)
+        off32 = off32 && t.t[i].x_span < (int64_t(1) << 32) && t.t[i].s_span < (int64_t(1) << 32);
+    if (off32) return launch_row_o<KT, DT, true>(mode, code16, rp, t, s);
     return launch_row_o<KT, DT, false>(mode, code16, rp, t, s);
 }
 
 template <int DT>
-hipError_t launch_row_dt(int kt, int mode, bool code16, const RowPass &rp, const Tile &t,
+hipError_t launch_row_dt(int kt, int mode, bool code16, const RowPass &rp, const TileSet &t,
                          hipStream_t s) {
     switch (kt) {
     case 16: return launch_row_t<16, DT>(mode, code16, rp, t, s);
@@ -933,7 +944,7 @@ hipError_t launch_perm_out_t(const void *yp, int64_t ld, const int32_t *vop, int
 
 // Per-storage-type entry points, explicitly instantiated in kernels_<type>.hip.
 template <int DT>
-hipError_t row_pass_dt(int kt, int mode, bool code16, const RowPass &rp, const Tile &t,
+hipError_t row_pass_dt(int kt, int mode, bool code16, const RowPass &rp, const TileSet &t,
                        hipStream_t s) {
     switch (kt) {
     case 16: return detail::launch_row_t<16, DT>(mode, code16, rp, t, s);
@@ -971,7 +982,7 @@ hipError_t permute_out_dt(int kt, const void *yp, int64_t ld, const int32_t *vop
 }
 
 #define ARROW_DECLARE_DT(DT_)                                                                  \
-    extern template hipError_t row_pass_dt<DT_>(int, int, bool, const RowPass &, const Tile &, \
+    extern template hipError_t row_pass_dt<DT_>(int, int, bool, const RowPass &, const TileSet &, \
                                                 hipStream_t);                                  \
     extern template hipError_t permute_in_dt<DT_>(int, const float *, int64_t, const int32_t *, \
                                                   int64_t, void *, int64_t, const float *,     \
@@ -980,7 +991,7 @@ hipError_t permute_out_dt(int kt, const void *yp, int64_t ld, const int32_t *vop
                                                    int64_t, const float *, const double *,      \
                                                    float *, int64_t, hipStream_t);
 #define ARROW_INSTANTIATE_DT(DT_)                                                              \
-    template hipError_t row_pass_dt<DT_>(int, int, bool, const RowPass &, const Tile &,        \
+    template hipError_t row_pass_dt<DT_>(int, int, bool, const RowPass &, const TileSet &,        \
                                          hipStream_t);                                         \
     template hipError_t permute_in_dt<DT_>(int, const float *, int64_t, const int32_t *,       \
                                            int64_t, void *, int64_t, const float *, unsigned *, \

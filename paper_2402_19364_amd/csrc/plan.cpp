@@ -588,18 +588,14 @@ struct ProfScope {
 
 }  // namespace
 
-arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
-    const int64_t n = p.n, k = op.k;
-    if (n == 0) return ARROW_OK;
-    const int kt = tile_width(k);
-    const int64_t es = elem_size(op.dtype);
-    const int64_t nb = final_parts(p, op.dtype);
-    char *w = static_cast<char *>(ws);
-    float *sbuf = reinterpret_cast<float *>(w);
-    w += align256((size_t)p.s_rows * k * 4);
-    double *psum = reinterpret_cast<double *>(w);
-    w += align256((size_t)k * nb * 8);
-    float *pmax = reinterpret_cast<float *>(w);
+arrow_status_t spmm_group(Plan &p, const OpState *ops, int nops, void *const *wss,
+                          hipStream_t s) {
+    const int64_t n = p.n;
+    if (n == 0 || nops == 0) return ARROW_OK;
+    const int dtype = ops[0].dtype;
+    const int kt = tile_width(ops[0].k);
+    const int64_t es = elem_size(dtype);
+    const int64_t nb = final_parts(p, dtype);
 
     RowPass ch{};
     set_geometry(ch, p.n_chunks, kChunksPerBlock, 1);
@@ -626,7 +622,7 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     upp.batch = p.up_batch;
 
     RowPass l0{};
-    set_geometry(l0, n, p.l0_rpb, l0_blocks_per_wg(op.dtype));
+    set_geometry(l0, n, p.l0_rpb, l0_blocks_per_wg(dtype));
     l0.ptr = p.l0_ptr;
     l0.idx = p.l0_idx;
     l0.val = p.l0_val;
@@ -644,51 +640,77 @@ arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
     l0.b = p.b;
     l0.batch = p.l0_batch;
 
-    for (int64_t c0 = 0; c0 < k; c0 += kt) {
-        Tile t{};
-        t.x = static_cast<const char *>(op.x) + c0 * es;
-        t.ldx = op.ldx;
-        t.x_span = ((n - 1) * op.ldx + kt) * es;
-        t.s = sbuf + c0;
-        t.s_out = sbuf + c0;
-        t.lds = k;
-        t.s_span = (p.s_rows * k - c0) * 4;
-        t.y = static_cast<char *>(op.y) + c0 * es;
-        t.ldy = op.ldy;
-        t.x_scale = op.x_scale ? op.x_scale + c0 : nullptr;
-        t.x_inv_norm = op.x_inv_norm ? op.x_inv_norm + c0 : nullptr;
-        t.x_maxabs = op.x_maxabs ? op.x_maxabs + c0 : nullptr;
-        t.y_scale = op.y_scale ? op.y_scale + c0 : nullptr;
-        t.part_sumsq = psum + c0 * nb;
-        t.part_max = pmax + c0 * nb;
-        t.part_ld = nb;
-        t.a_inf = (float)p.a_inf;
+    // every column tile of every operand; launches take up to kMaxTiles each
+    std::vector<Tile> tiles;
+    for (int o = 0; o < nops; ++o) {
+        const OpState &op = ops[o];
+        const int64_t k = op.k;
+        char *w = static_cast<char *>(wss[o]);
+        float *sbuf = reinterpret_cast<float *>(w);
+        w += align256((size_t)p.s_rows * k * 4);
+        double *psum = reinterpret_cast<double *>(w);
+        w += align256((size_t)k * nb * 8);
+        float *pmax = reinterpret_cast<float *>(w);
+        for (int64_t c0 = 0; c0 < k; c0 += kt) {
+            Tile t{};
+            t.x = static_cast<const char *>(op.x) + c0 * es;
+            t.ldx = op.ldx;
+            t.x_span = ((n - 1) * op.ldx + kt) * es;
+            t.s = sbuf + c0;
+            t.s_out = sbuf + c0;
+            t.lds = k;
+            t.s_span = (p.s_rows * k - c0) * 4;
+            t.y = static_cast<char *>(op.y) + c0 * es;
+            t.ldy = op.ldy;
+            t.x_scale = op.x_scale ? op.x_scale + c0 : nullptr;
+            t.x_inv_norm = op.x_inv_norm ? op.x_inv_norm + c0 : nullptr;
+            t.x_maxabs = op.x_maxabs ? op.x_maxabs + c0 : nullptr;
+            t.y_scale = op.y_scale ? op.y_scale + c0 : nullptr;
+            t.part_sumsq = psum + c0 * nb;
+            t.part_max = pmax + c0 * nb;
+            t.part_ld = nb;
+            t.a_inf = (float)p.a_inf;
+            tiles.push_back(t);
+        }
+    }
+    for (size_t t0 = 0; t0 < tiles.size(); t0 += kMaxTiles) {
+        TileSet ts{};
+        ts.n = (int32_t)std::min<size_t>(kMaxTiles, tiles.size() - t0);
+        for (int i = 0; i < ts.n; ++i) ts.t[i] = tiles[t0 + i];
         if (p.n_chunks > 0) {
             ProfScope ps(p, ARROW_KERNEL_CHUNKS, s);
-            LAUNCH_OK(launch_row_pass(kt, op.dtype, kPassChunk, false, ch, t, s));
+            LAUNCH_OK(launch_row_pass(kt, dtype, kPassChunk, false, ch, ts, s));
         }
         if (p.n_up > 0) {
             ProfScope ps(p, ARROW_KERNEL_UPPER, s);
-            LAUNCH_OK(launch_row_pass(kt, op.dtype, kPassUpper, false, upp, t, s));
+            LAUNCH_OK(launch_row_pass(kt, dtype, kPassUpper, false, upp, ts, s));
         }
         {
             ProfScope ps(p, ARROW_KERNEL_LEVEL0, s);
-            LAUNCH_OK(launch_row_pass(kt, op.dtype, kPassLevel0, p.code16, l0, t, s));
+            LAUNCH_OK(launch_row_pass(kt, dtype, kPassLevel0, p.code16, l0, ts, s));
         }
     }
-    NormArgs na{};
-    na.part_sumsq = psum;
-    na.part_max = (op.y_maxabs != nullptr) ? pmax : nullptr;
-    na.part_ld = nb;
-    na.nparts = (int32_t)nb;
-    na.norm = op.y_norm;
-    na.inv_norm = op.y_inv_norm;
-    na.maxabs = op.y_maxabs;
-    if (op.y_norm || op.y_inv_norm || op.y_maxabs) {
+    for (int o = 0; o < nops; ++o) {
+        const OpState &op = ops[o];
+        if (!(op.y_norm || op.y_inv_norm || op.y_maxabs)) continue;
+        char *w = static_cast<char *>(wss[o]) + align256((size_t)p.s_rows * op.k * 4);
+        NormArgs na{};
+        na.part_sumsq = reinterpret_cast<double *>(w);
+        na.part_max = op.y_maxabs ? reinterpret_cast<float *>(w + align256((size_t)op.k * nb * 8))
+                                  : nullptr;
+        na.part_ld = nb;
+        na.nparts = (int32_t)nb;
+        na.norm = op.y_norm;
+        na.inv_norm = op.y_inv_norm;
+        na.maxabs = op.y_maxabs;
         ProfScope ps(p, ARROW_KERNEL_NORM, s);
-        LAUNCH_OK(launch_norm(na, (int)k, s));
+        LAUNCH_OK(launch_norm(na, (int)op.k, s));
     }
     return ARROW_OK;
+}
+
+arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s) {
+    return spmm_group(p, &op, 1, &ws, s);
 }
 
 int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
@@ -751,7 +773,10 @@ arrow_status_t plain_csr(int64_t n, const int32_t *row_ptr, const int32_t *col, 
         t.ldy = ld;
         t.part_sumsq = ws ? ws + c0 * nb : nullptr;
         t.part_ld = nb;
-        LAUNCH_OK(launch_row_pass(kt, kF32, kPassPlain, false, rp, t, s));
+        TileSet ts{};
+        ts.t[0] = t;
+        ts.n = 1;
+        LAUNCH_OK(launch_row_pass(kt, kF32, kPassPlain, false, rp, ts, s));
     }
     if (ws && norms) {
         NormArgs na{};

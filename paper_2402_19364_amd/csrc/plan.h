@@ -113,6 +113,12 @@ int tile_width(int64_t k);
 size_t op_workspace(const Plan &p, int64_t k, int dtype);
 // Enqueue one product for one operand; `ws` holds op_workspace bytes.
 arrow_status_t spmm_one(Plan &p, const OpState &op, void *ws, hipStream_t s);
+// One product for each of `nops` operands of one storage type and one tile
+// width, as one launch sequence over all their column tiles (the matrix is
+// read once per launch); wss[o] holds op_workspace bytes for operand o.  Every
+// operand's result is bitwise the one spmm_one gives it alone.
+arrow_status_t spmm_group(Plan &p, const OpState *ops, int nops, void *const *wss,
+                          hipStream_t s);
 int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype);
 
 // Gather batch for a row pass from its rows' entry counts (ptr, host) and

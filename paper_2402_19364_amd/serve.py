@@ -10,8 +10,11 @@ feature width k, a storage dtype and an iteration count T.  The server
   budget -- requests that arrive while others run join at the next iteration
   boundary of their group,
 * batches all active requests of one (graph, dtype) into one product call per
-  iteration (one operand per request) on that group's stream; different groups
-  run on different streams, so their work overlaps on the device,
+  iteration (one operand per request) on that group's stream; the library runs
+  the operands of one tile width as one launch sequence over all their column
+  tiles, so the matrix is read once per iteration for the whole group (a wider
+  effective k); different groups run on different streams, so their work
+  overlaps on the device,
 * finishes a request after its T products: X_T = Y_{T-1} / ||Y_{T-1}||_col is
   permuted back to the original order and copied to the host.
 
@@ -115,7 +118,9 @@ class Server:
             self.used -= fp
         if graph not in self.plans:
             handle = self.engine.load_plan(graph, self.graphs[graph])
-            fp = self.engine.plan_footprint(self.graphs[graph])
+            # account the plan's actual device bytes (the estimate only gates
+            # admission before the plan exists; it is an upper bound)
+            fp = self.engine.plan_bytes(handle)
             self.plans[graph] = (handle, fp)
             self.used += fp
         self.plans.move_to_end(graph)
@@ -233,15 +238,25 @@ class GpuEngine:
         self.dev = torch.device(f"cuda:{device}")
         self._plans: Dict[str, object] = {}
         self._fp: Dict[int, int] = {}
+        # plan buffers come from PyTorch's caching allocator (process-wide
+        # setting): evicting a plan returns its memory to the pool without a
+        # device synchronisation
+        arrow.use_torch_allocator()
 
     # plans
     def plan_footprint(self, decomposition) -> int:
+        """Upper bound of a plan's device bytes, before it exists: per entry at
+        most a 4-byte column or 2-byte code plus a 6-byte far-table slot and the
+        4-byte value; per row the entry and list offsets, the permutation, the
+        processing order and a listed partial row."""
         key = id(decomposition)
         if key not in self._fp:
             info = decomposition.info()
-            # the plan holds ~ (4 + 2..4 + 4) bytes per entry plus ~16 bytes per row
             self._fp[key] = int(info["nnz"] * 12 + info["n"] * 24 + (1 << 20))
         return self._fp[key]
+
+    def plan_bytes(self, plan) -> int:
+        return int(plan.footprint())
 
     def load_plan(self, name: str, decomposition):
         plan = self.arrow.Plan(decomposition, self.device)
@@ -249,9 +264,10 @@ class GpuEngine:
         return plan
 
     def free_plan(self, name: str) -> None:
+        # only idle plans are evicted: every product that used it has completed
+        # (its group's event was observed), so no kernel still reads it
         plan = self._plans.pop(name, None)
         if plan is not None:
-            self.torch.cuda.synchronize(self.dev)
             plan.close()
 
     # requests
@@ -330,7 +346,10 @@ class GpuEngine:
             time.sleep(min(delay, 0.005))
 
     def wait_any(self, events) -> None:
-        events[0].synchronize()
+        """Return as soon as any of the events has completed (polling, so a
+        long step of one group does not hold up the others)."""
+        while not any(ev.query() for ev in events):
+            time.sleep(20e-6)
 
     def finish(self, plan, st, req: Request, stream):
         torch = self.torch

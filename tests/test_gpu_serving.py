@@ -65,6 +65,11 @@ def test_alone_equals_mix_and_oracle():
         srv.register_graph(name, d)
     done = srv.run(reqs)
     assert len(done) == len(reqs)
+    # the admission estimate of every plan bounds its actual device bytes
+    for name, (handle, fp) in srv.plans.items():
+        est = srv.engine.plan_footprint(decs[name])
+        say(f"[serving] plan {name}: {fp} bytes, admission estimate {est}")
+        assert fp == handle.footprint() <= est
     assert srv.max_group_width >= 2, "no batching happened"
     stats = latency_stats(done)
     say(f"[serving] mix: p50 {stats['p50_ms']:.2f} ms p99 {stats['p99_ms']:.2f} ms, "

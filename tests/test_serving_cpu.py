@@ -25,6 +25,7 @@ class SimEngine:
     member; results are a deterministic function of the request's own input."""
 
     def __init__(self, step_time=1.0, per_member=0.25):
+        self.plan_fp = {}
         self.now = 0.0
         self.step_time = step_time
         self.per_member = per_member
@@ -41,7 +42,11 @@ class SimEngine:
     def load_plan(self, name, d):
         self.loaded.append(name)
         self.live_plans.add(name)
+        self.plan_fp[name] = self.plan_footprint(d)
         return name
+
+    def plan_bytes(self, handle):
+        return self.plan_fp[handle]
 
     def free_plan(self, name):
         self.freed.append(name)
