@@ -139,6 +139,24 @@ typedef struct {
 arrow_status_t arrow_decomp_level_stats(arrow_decomp_t d, int32_t level,
                                         arrow_level_stats_t *out);
 
+/*
+ * Nonzero blocks of level `level` in a grid of s x s blocks (s >= 1): the
+ * number of blocks that hold at least one entry (with s = b these are the
+ * b x b tiles of Section 4.1, the count Section 7 compares with a 1.5D
+ * decomposition) and a histogram of their densities (entries / s^2):
+ * hist[j] counts blocks with density in [j/10, (j+1)/10), hist[9] also those
+ * of density 1.  region 0 takes every entry, region 1 only the head rows and
+ * columns (row or column < b).  With s = 16 the histogram shows whether any
+ * head tile is dense enough for a matrix-core product.  Host only.
+ */
+typedef struct {
+    int64_t nonzero_blocks, entries;
+    double max_density;
+    int64_t hist[10];
+} arrow_block_stats_t;
+arrow_status_t arrow_decomp_block_stats(arrow_decomp_t d, int32_t level, int32_t s,
+                                        int32_t region, arrow_block_stats_t *out);
+
 /* Versioned binary file with a checksum; load rejects corrupt files (ARROW_ERR_IO). */
 arrow_status_t arrow_decomp_save(arrow_decomp_t d, const char *path);
 arrow_status_t arrow_decomp_load(const char *path, arrow_decomp_t *out);

@@ -61,6 +61,7 @@ def _load():
         "arrow_plan_info": [P, P],
         "arrow_plan_footprint": [P, ctypes.POINTER(SZ)],
         "arrow_decomp_level_stats": [P, I32, P],
+        "arrow_decomp_block_stats": [P, I32, I32, I32, P],
         "arrow_plan_kernel_bytes": [P, I32, I64, I32, ctypes.POINTER(I64)],
         "arrow_workspace_size": [P, I64, I32, ctypes.POINTER(SZ)],
         "arrow_iterate_workspace_size": [P, I64, I32, ctypes.POINTER(SZ)],
@@ -123,6 +124,11 @@ class _DecompInfo(ctypes.Structure):
 class _LevelStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n_i", "nnz_i", "head_row_nnz", "head_col_nnz",
                                               "band_nnz", "active_rows")]
+
+
+class _BlockStats(ctypes.Structure):
+    _fields_ = [("nonzero_blocks", ctypes.c_int64), ("entries", ctypes.c_int64),
+                ("max_density", ctypes.c_double), ("hist", ctypes.c_int64 * 10)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -237,6 +243,15 @@ class Decomposition:
         st = _LevelStats()
         _check(_load().arrow_decomp_level_stats(self._h, i, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in _LevelStats._fields_}
+
+    def block_stats(self, i: int, s: int, head_only: bool = False) -> dict:
+        """Nonzero s x s blocks of level i and the histogram of their densities
+        (tenths); head_only restricts to the head rows and columns."""
+        st = _BlockStats()
+        _check(_load().arrow_decomp_block_stats(self._h, i, s, 1 if head_only else 0,
+                                                ctypes.byref(st)))
+        return {"nonzero_blocks": st.nonzero_blocks, "entries": st.entries,
+                "max_density": st.max_density, "hist": list(st.hist)}
 
     def levels(self) -> list:
         return [self.level(i) for i in range(self.info()["levels"])]

@@ -1,6 +1,7 @@
 // extern "C" boundary of libarrow: argument checks, error reporting, handles.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -167,6 +168,50 @@ arrow_status_t arrow_decomp_level_stats(arrow_decomp_t d, int32_t level,
                 ++st.head_col_nnz;
             else
                 ++st.band_nnz;
+        }
+    }
+    *out = st;
+    return ARROW_OK;
+}
+
+arrow_status_t arrow_decomp_block_stats(arrow_decomp_t d, int32_t level, int32_t s,
+                                        int32_t region, arrow_block_stats_t *out) {
+    if (!d || !out) {
+        set_error("NULL argument");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (level < 0 || level >= (int32_t)d->d.levels.size()) {
+        set_error("level out of range");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    if (s < 1 || (region != 0 && region != 1)) {
+        set_error("block size must be >= 1 and region 0 or 1");
+        return ARROW_ERR_INVALID_ARG;
+    }
+    const arrow::Level &L = d->d.levels[level];
+    const int64_t b = d->d.b;
+    arrow_block_stats_t st{};
+    std::vector<int64_t> cols;
+    const double area = (double)s * (double)s;
+    for (int64_t r0 = 0; r0 < L.n_i; r0 += s) {
+        // block columns of the entries of block row r0 / s, counted by sorting
+        cols.clear();
+        for (int64_t p = r0; p < std::min<int64_t>(L.n_i, r0 + s); ++p)
+            for (int64_t e = L.row_ptr[p]; e < L.row_ptr[p + 1]; ++e) {
+                const int64_t q = L.col[e];
+                if (region == 1 && !(p < b || q < b)) continue;
+                cols.push_back(q / s);
+            }
+        std::sort(cols.begin(), cols.end());
+        st.entries += (int64_t)cols.size();
+        for (size_t i = 0; i < cols.size();) {
+            size_t j = i;
+            while (j < cols.size() && cols[j] == cols[i]) ++j;
+            const double dens = (double)(j - i) / area;
+            st.max_density = std::max(st.max_density, dens);
+            ++st.hist[std::min(9, (int)(dens * 10.0))];
+            ++st.nonzero_blocks;
+            i = j;
         }
     }
     *out = st;

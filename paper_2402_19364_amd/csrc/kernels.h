@@ -12,6 +12,9 @@ enum : int { kPassChunk = 0, kPassUpper = 1, kPassLevel0 = 2, kPassPlain = 3 };
 constexpr int kMaxBlockRows = 256;   // rows per staged block (at most)
 constexpr int kStageEntries = 2048;  // matrix entries staged in LDS per block
 constexpr int kStageLists = 512;     // listed partial rows staged in LDS per block
+// far-column table entries staged in LDS per block: short-batch passes,
+// wide-batch passes (the plan keeps every block's table within the larger)
+constexpr int kStageFar = 1024, kStageFarWide = 2048;
 constexpr int kChunk = 64;           // entries per chunk of a head row or long row
 // Gather batch of a row pass.  kBatchWide gathers 8 entries of a row per batch
 // and up to 8 listed partial rows at a time; a short batch u in
@@ -41,13 +44,10 @@ struct RowPass {
     const int32_t *blk_e; // [blocks + 1] entry offset of each block (ptr at the
                           // block starts), or null
     const int32_t *blk_c; // [blocks + 1] list offset of each block (with blk_e)
-    // level-0 pass with 16-bit codes: code 3b+1+j names entry j of the block's
-    // far-column table fcol[fptr[block] ...]; fpos gives the entry's index
-    // within the block, so a staged block scatters the table next to its
-    // entries in LDS (null: no far entries)
+    // level-0 pass with 16-bit codes: code 3b+1+j names entry j of the
+    // block's far-column table fcol[fptr[block] ...] (null: no far entries)
     const int32_t *fptr;
     const int32_t *fcol;
-    const uint16_t *fpos;
     int32_t b;
     int32_t out_row0;     // first partial-buffer row written by this pass
     int32_t batch;        // kBatchWide or a short batch in [kBatchMin, kBatchMax]

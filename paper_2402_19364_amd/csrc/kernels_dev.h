@@ -24,7 +24,8 @@
 //                |code| for scaled formats).
 //   norm pass    fixed-order FP64 reduction of the block partials per column.
 //
-// Lane layout: every lane owns 16 bytes of an X row (8 bytes for FP8), VEC
+// Lane layout: every lane owns 16 bytes of an X row (8 bytes for FP8 in the row
+// passes, 16 in the chunk pass), VEC
 // elements; LPR = KT / VEC lanes cover a row's column tile, a wave handles
 // 64 / LPR rows at a time.  Matrix entries and X rows are read with plain loads (X rows are
 // reused through L2 by neighbouring rows of the band); Y is written with
@@ -199,6 +200,51 @@ template <> struct Fmt<kF8E4M3> {
     }
 };
 
+// FP8 with 16 values per lane, for the chunk pass: its gathers then move
+// 16 bytes like those of the other formats (it keeps no per-column state, so
+// the wider lanes cost few registers there; the row passes keep 8 values).
+struct FmtF8Wide {
+    using Raw = vu4;  // 16 values per lane: a gather moves 16 bytes like the other formats
+    static constexpr int kVec = 16;
+    static constexpr int kBytes = 16;
+    static constexpr float kMax = 448.0f;
+    static constexpr bool kScaled = true;
+    // gfx950 converts OCP E4M3FN in hardware, two values per instruction
+    __device__ static void decode(vu4 a, float (&v)[kVec]) {
+        uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+            const v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+            v[4 * i] = lo.x;
+            v[4 * i + 1] = lo.y;
+            v[4 * i + 2] = hi.x;
+            v[4 * i + 3] = hi.y;
+        }
+    }
+    // round to nearest even; inputs are clamped to +-448 first (the scale
+    // guarantees |v| <= 448 up to rounding, and the format has no infinity)
+    __device__ static void store(void *p, float (&v)[kVec]) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float c[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] = fminf(fmaxf(v[4 * i + j], -448.0f), 448.0f);
+            int pk = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+            pk = __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], pk, true);
+            w[i] = (uint32_t)pk;
+        }
+        vu4 a = {w[0], w[1], w[2], w[3]};
+        store_nt(p, a);
+        decode(a, v);
+    }
+};
+
+// Format of the chunk pass's gathers.
+template <int DT> struct GatherFmt { using type = Fmt<DT>; };
+template <> struct GatherFmt<kF8E4M3> { using type = FmtF8Wide; };
+
 // Smallest power of two >= x (x > 0, finite); 1 for x <= 0.
 __device__ __forceinline__ float pow2_ceil(double x) {
     if (!(x > 0.0)) return 1.0f;
@@ -264,8 +310,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     __shared__ int32_t s_cidx[CONTRIB ? kStageLists : 1];
     __shared__ IdxT s_idx[kStageEntries];
     __shared__ float s_val[kStageEntries];
-    // far columns of the staged entries (valid where the code is a far code)
-    __shared__ int32_t s_fcol[FAR ? kStageEntries : 1];
+    // the block's far-column table (code 3b+1+j names entry j); short
+    // batches (uniform short rows, few folded entries) keep a smaller table
+    // so that more workgroups share the LDS
+    constexpr int STAGE_FAR = BATCH == kBatchWide ? kStageFarWide : kStageFar;
+    __shared__ int32_t s_ftab[FAR ? STAGE_FAR : 1];
     __shared__ int32_t s_fb[2];
 
     const int wg = row_block(blockIdx.x / ts.n);
@@ -378,19 +427,17 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
                 nf = __builtin_amdgcn_readfirstlane(s_fb[1]) - fb;
             }
         }
-        // Block-uniform choice: the block's entries come from LDS when they fit,
-        // otherwise every entry is read from global memory.
-        const bool staged = ne <= kStageEntries;
+        // Block-uniform choice: the block's entries and its far-column table
+        // come from LDS when they fit, otherwise every one is read from global
+        // memory.
+        const bool staged = ne <= kStageEntries && (!FAR || nf <= STAGE_FAR);
         if (staged) {
             for (int i = tid; i < ne; i += kBlockThreads) {
                 s_idx[i] = gidx[e0 + i];
                 s_val[i] = rp.val[e0 + i];
             }
             if constexpr (FAR) {
-                for (int i = tid; i < nf; i += kBlockThreads) {  // nf <= ne, every fpos < ne
-                    const int pos = rp.fpos[fb + i];
-                    s_fcol[pos < kStageEntries ? pos : kStageEntries - 1] = rp.fcol[fb + i];
-                }
+                for (int i = tid; i < nf; i += kBlockThreads) s_ftab[i] = rp.fcol[fb + i];
             }
         }
         // the block's list of partial rows, staged the same way
@@ -456,10 +503,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
                     }
                     if constexpr (FAR) {
                         // the batch's folded entries (waves whose batch has none
-                        // skip this): a staged block scattered their columns beside
-                        // the codes; otherwise the block's table is read directly
-                        // (index clamped to the table's first entry, which exists
-                        // since the wave's batch holds a far code)
+                        // skip this): their columns from the block's far-column
+                        // table, staged in LDS or read directly (index clamped to
+                        // the table's first entry, which exists since the wave's
+                        // batch holds a far code)
                         if (__builtin_amdgcn_ballot_w64(anyfar)) {
 #pragma unroll
                             for (int u = 0; u < UNR; ++u) {
@@ -467,7 +514,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
                                 int cc, far;
                                 if constexpr (STAGED) {
                                     cc = s_idx[ee];
-                                    far = s_fcol[ee];
+                                    const int fi = cc - 3 * rp.b - 1;
+                                    far = s_ftab[fi > 0 ? fi : 0];
                                 } else {
                                     cc = gidx[e0 + ee];
                                     const int fi = cc - 3 * rp.b - 1;
@@ -647,7 +695,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
 template <int KT, int DT, bool OFF32>
 __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, TileSet ts) {
     const Tile &t = ts.t[blockIdx.x % ts.n];
-    using F = Fmt<DT>;
+    using F = typename GatherFmt<DT>::type;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;
     constexpr int RPW = kWave / LPR;                 // lane groups per wave

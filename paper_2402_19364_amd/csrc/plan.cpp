@@ -233,7 +233,9 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     // sigma_i), as long as the row stays within kFuseRow entries and the
     // 16-bit codes 3b+1+j of the block's far-column table have room.  The
     // rest keep the upper pass and reach the level-0 row as partial rows.
-    const int64_t far_cap = p.code16 ? 65535 - 3 * (int64_t)b : INT64_MAX;
+    // (and the block's table fits the kernel's LDS staging)
+    const int64_t far_cap =
+        p.code16 ? std::min<int64_t>(65535 - 3 * (int64_t)b, kStageFarWide) : INT64_MAX;
     std::vector<uint8_t> fused(vrows.size(), 0);
     for (int64_t blk = 0; blk < nblocks_of(n, rpb0); ++blk) {
         int64_t far = 0;
@@ -295,7 +297,6 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     std::vector<int32_t> l0_col;
     std::vector<float> l0_val;
     std::vector<int32_t> far_ptr(nblocks_of(n, rpb0) + 1, 0), far_col;
-    std::vector<uint16_t> far_pos;  // entry index of each far entry within its block
     std::vector<uint8_t> seen_l0(n, 0), seen_up(n, 0), seen_ch(n, 0);
     for (int64_t r = 0; r < n; ++r) {
         const int64_t blk = r / rpb0;
@@ -311,7 +312,6 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
                 const int64_t q = L0.col[e];
                 if (p.code16 && q > r + b) {  // a head row's column beyond the band
                     const int64_t j = (int64_t)far_col.size() - far_ptr[blk];
-                    far_pos.push_back((uint16_t)((int64_t)l0_val.size() - l0_ptr[blk * rpb0]));
                     l0_code.push_back((uint16_t)(3 * (int64_t)b + 1 + j));
                     far_col.push_back((int32_t)q);
                 } else if (p.code16) {
@@ -331,8 +331,6 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
                     const int32_t c = pos0[L.vop[L.col[e]]];
                     if (p.code16) {
                         const int64_t j = (int64_t)far_col.size() - far_ptr[blk];
-                        far_pos.push_back((uint16_t)((int64_t)l0_val.size() -
-                                                     l0_ptr[blk * rpb0]));
                         l0_code.push_back((uint16_t)(3 * (int64_t)b + 1 + j));
                         far_col.push_back(c);
                     } else {
@@ -495,7 +493,6 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     if (p.l0_nfar > 0) {
         UP(p.l0_fptr, far_ptr);
         UP(p.l0_fcol, far_col);
-        UP(p.l0_fpos, far_pos);
     }
     UP(p.up_ptr, up_ptr);
     UP(p.up_col, up_col);
@@ -636,7 +633,6 @@ arrow_status_t spmm_group(Plan &p, const OpState *ops, int nops, void *const *ws
     l0.blk_c = p.l0_batch != kBatchWide ? p.l0_blk_c : nullptr;
     l0.fptr = p.l0_fptr;
     l0.fcol = p.l0_fcol;
-    l0.fpos = p.l0_fpos;
     l0.b = p.b;
     l0.batch = p.l0_batch;
 
@@ -734,7 +730,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
                (p.n + 1) * (p.l0_ncontrib > 0 || p.l0_batch == kBatchWide ? 8 : 4) +
                (p.l0_order ? p.n : 0) +
                (p.l0_batch != kBatchWide ? (nblocks_of(p.n, p.l0_rpb) + 1) * 8 : 0) +
-               (p.l0_nfar > 0 ? p.l0_nfar * 6 + (nblocks_of(p.n, p.l0_rpb) + 1) * 4 : 0) +
+               (p.l0_nfar > 0 ? p.l0_nfar * 4 + (nblocks_of(p.n, p.l0_rpb) + 1) * 4 : 0) +
                p.l0_ncontrib * (4 + k * 4) + p.distinct_l0 * k * sx + p.n * k * sx +
                nb * k * (8 + (scaled ? 4 : 0)) + k * (scaled ? 16 : 8);
     case ARROW_KERNEL_NORM:

@@ -15,9 +15,9 @@ constexpr int kLongRow = 32;      // rows with more entries go through the chunk
 constexpr int kFuseRow = 64;      // longest level-0 row after folding in rows of levels >= 1
 constexpr int kRowsPerBlock = kMaxBlockRows;       // rows per staged block
 constexpr int kBlocksPerWg = 1;                    // blocks walked by one workgroup
-// The level-0 pass of the scaled formats (FP16, FP8) walks 4 blocks per
-// workgroup: its per-workgroup prologue (per-column output scales) is longer.
-constexpr int kBlocksPerWgScaled = 4;
+// Blocks walked by one workgroup of the level-0 pass of the scaled formats
+// (FP16, FP8), whose prologue also derives the per-column output scales.
+constexpr int kBlocksPerWgScaled = 1;
 constexpr int kChunksPerBlock = 4;                // chunks per workgroup (one per wave)
 
 struct ProfRec {
@@ -56,7 +56,6 @@ struct Plan {
     int32_t l0_rpb = kMaxBlockRows;     // rows per staged block of the level-0 pass
     int32_t *l0_fptr = nullptr;         // [blocks + 1] far-column table of each block
     int32_t *l0_fcol = nullptr;         // pi_0 columns of entries folded in from levels >= 1
-    uint16_t *l0_fpos = nullptr;        // their entry index within the block
     int64_t l0_nfar = 0;                // entries in the far-column tables
     int64_t fused_rows = 0;             // rows of levels >= 1 folded into level-0 rows
     // upper pass (rows of levels >= 1 with entries)

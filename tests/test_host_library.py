@@ -270,3 +270,28 @@ def test_allocator_and_threads_arguments():
     ref = _lib_decompose(A, 16, seed=4).levels()
     for t in (1, 2, 3, 8):
         _assert_same(A_.Decomposition.from_matrix(A, 16, seed=4, threads=t).levels(), ref)
+
+
+def test_block_stats_match_a_brute_force_count():
+    A = W.make_matrix("rmat", 11, "row_normalized", 7, 8, 16)
+    b = 32
+    d = _lib_decompose(A, b, seed=2)
+    for i, L in enumerate(d.levels()[:3]):
+        rows = np.repeat(np.arange(L["n_i"]), np.diff(L["row_ptr"]))
+        col = L["col"].astype(np.int64)
+        for s in (1, 4, 16, b):
+            for head in (False, True):
+                keep = (rows < b) | (col < b) if head else np.ones(col.size, bool)
+                keys = (rows[keep] // s) * (L["n_i"] // s + 1) + col[keep] // s
+                _, counts = np.unique(keys, return_counts=True)
+                dens = counts / float(s * s)
+                hist = np.bincount(np.minimum((dens * 10).astype(int), 9), minlength=10)
+                st = d.block_stats(i, s, head_only=head)
+                assert st["nonzero_blocks"] == counts.size and st["entries"] == int(keep.sum())
+                assert st["hist"] == hist.tolist(), (i, s, head)
+                assert st["max_density"] == (dens.max() if dens.size else 0.0)
+    # one-entry blocks: every nonzero 1 x 1 block has density 1
+    st = d.block_stats(0, 1)
+    assert st["nonzero_blocks"] == st["entries"] == st["hist"][9]
+    with pytest.raises(A_.ArrowError):
+        d.block_stats(0, 0)
