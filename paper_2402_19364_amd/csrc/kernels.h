@@ -16,6 +16,11 @@ constexpr int kStageLists = 512;     // listed partial rows staged in LDS per bl
 // wide-batch passes (the plan keeps every block's table within the larger)
 constexpr int kStageFar = 1024, kStageFarWide = 2048;
 constexpr int kChunk = 64;           // entries per chunk of a head row or long row
+constexpr int kXcds = 8;             // XCDs of an MI355X; dispatch sends workgroup i to XCD i % 8
+#ifndef ARROW_CHUNKS_PER_WAVE
+#define ARROW_CHUNKS_PER_WAVE 2
+#endif
+constexpr int kChunksPerWave = ARROW_CHUNKS_PER_WAVE;  // consecutive chunks reduced by one wave
 // Gather batch of a row pass.  kBatchWide gathers 8 entries of a row per batch
 // and up to 8 listed partial rows at a time; a short batch u in
 // [kBatchMin, kBatchMax] gathers u entries per batch and partial rows 2 at a

@@ -687,23 +687,39 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     }
 }
 
-// Chunk pass: each wave reduces one chunk (at most kChunk entries of a head
-// row or long row).  Its lane groups take interleaved entries, so all the
-// chunk's X-row gathers are in flight together; the group sums are combined
-// by a fixed butterfly over the group bits and group 0 writes the FP32
-// partial row.  A workgroup handles rows_per_block consecutive chunks.
+// Chunk pass: each wave reduces kChunksPerWave consecutive chunks (at most
+// kChunk entries each, of a head row or long row) one after the other.  A
+// chunk's entries arrive with one coalesced load (lane j holds entry j), and
+// the next chunk's entries are loaded while the current chunk's X rows are
+// gathered, so a chunk costs one memory round trip.  The lane groups take
+// interleaved entries (group g: entries g, g + RPW, ...; handed over by
+// cross-lane reads), so all of a chunk's gathers are in flight together; the
+// group sums are combined by a fixed butterfly over the group bits and group
+// 0 writes the FP32 partial row.  A workgroup handles rows_per_block =
+// kWaves * kChunksPerWave consecutive chunks.
+#ifndef ARROW_CHUNK_WAVES
+#define ARROW_CHUNK_WAVES 1
+#endif
 template <int KT, int DT, bool OFF32>
-__global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, TileSet ts) {
-    const Tile &t = ts.t[blockIdx.x % ts.n];
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(
+    ARROW_CHUNK_WAVES))) void chunk_kernel(RowPass rp, TileSet ts) {
+    // workgroup i runs on XCD i % kXcds and takes unit (i / kXcds / n) * kXcds
+    // + i % kXcds of tile (i / kXcds) % n, so every tile of a unit runs on the
+    // XCD the plan placed the unit on (the grid is a multiple of kXcds
+    // workgroups per tile)
+    const int xcd = blockIdx.x % kXcds;
+    const int rest = blockIdx.x / kXcds;
+    const Tile &t = ts.t[rest % ts.n];
     using F = typename GatherFmt<DT>::type;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;
     constexpr int RPW = kWave / LPR;                 // lane groups per wave
     constexpr int PER = (kChunk + RPW - 1) / RPW;    // entries per group and chunk
     constexpr int UNR = PER < 8 ? PER : 8;
+    static_assert(kChunk == kWave && PER % UNR == 0, "chunk layout");
     constexpr int kElem = DT == kF32 ? 4 : (DT == kF8E4M3 ? 1 : 2);
     using Off = typename std::conditional<OFF32, uint32_t, uint64_t>::type;
-    const int wg = row_block(blockIdx.x / ts.n);
+    const int wg = (rest / ts.n) * kXcds + xcd;
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const int g = lane / LPR;
@@ -712,25 +728,49 @@ __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, TileSe
     const char *xbase = reinterpret_cast<const char *>(t.x);
     const Off xstride = (Off)(t.ldx * kElem);
     const Off xlane = (Off)(sub * F::kBytes);
-    const int64_t c_begin = (int64_t)wg * rp.rows_per_block;
-    const int64_t c_end =
-        c_begin + rp.rows_per_block < rp.nrows ? c_begin + rp.rows_per_block : rp.nrows;
-    for (int64_t ci = c_begin + wave; ci < c_end; ci += kWaves) {
-        const int e0 = rp.ptr[ci], e1 = rp.ptr[ci + 1];
+    const int64_t c0 = ((int64_t)wg * kWaves + wave) * kChunksPerWave;
+    if (c0 >= rp.nrows) return;
+    // chunk bounds: lane i <= kChunksPerWave holds ptr[min(c0 + i, nrows)]
+    int bnd = 0;
+    if (lane <= kChunksPerWave) bnd = rp.ptr[c0 + lane < rp.nrows ? c0 + lane : rp.nrows];
+    // entries of chunk i: lane j holds entry j (column 0, value 0 past its end)
+    auto fetch = [&](int i, int &col, float &val) {
+        const int e0 = __builtin_amdgcn_readlane(bnd, i);
+        const int e1 = __builtin_amdgcn_readlane(bnd, i + 1);
+        col = 0;
+        val = 0.0f;
+        if (e0 + lane < e1) {
+            col = gidx[e0 + lane];
+            val = rp.val[e0 + lane];
+        }
+    };
+    int col, ncol = 0;
+    float val, nval = 0.0f;
+    fetch(0, col, val);
+    for (int i = 0; i < kChunksPerWave; ++i) {
+        // an empty slot (or one past the end of the pass) holds no entries
+        const int len = __builtin_amdgcn_readlane(bnd, i + 1) - __builtin_amdgcn_readlane(bnd, i);
+        if (i + 1 < kChunksPerWave) fetch(i + 1, ncol, nval);
+        if (len <= 0) {
+            col = ncol;
+            val = nval;
+            continue;
+        }
         float acc[VEC];
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-        for (int e = e0 + g; e < e1; e += RPW * UNR) {
+        for (int k = 0; k < VEC; ++k) acc[k] = 0.0f;
+        for (int u0 = 0; u0 < PER && RPW * u0 < len; u0 += UNR) {
             float av[UNR];
             Off off[UNR];
             bool ok[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
-                const int ee = e + u * RPW;
-                ok[u] = ee < e1;
-                const int es = ok[u] ? ee : e;
-                av[u] = ok[u] ? rp.val[es] : 0.0f;
-                off[u] = (Off)gidx[es] * xstride + xlane;
+                const int j = g + RPW * (u0 + u);  // < kWave
+                ok[u] = j < len;
+                const int cj = __shfl(col, j);
+                const float vj = __shfl(val, j);
+                av[u] = ok[u] ? vj : 0.0f;
+                off[u] = (Off)cj * xstride + xlane;
             }
             typename F::Raw xr[UNR];
 #pragma unroll
@@ -741,20 +781,22 @@ __global__ __launch_bounds__(kBlockThreads) void chunk_kernel(RowPass rp, TileSe
                 float xv[VEC];
                 F::decode(w, xv);
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[i] = fmaf(av[u], xv[i], acc[i]);
+                for (int k = 0; k < VEC; ++k) acc[k] = fmaf(av[u], xv[k], acc[k]);
             }
         }
 #pragma unroll
         for (int off = LPR; off < kWave; off <<= 1)
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] += __shfl_xor(acc[i], off);
+            for (int k = 0; k < VEC; ++k) acc[k] += __shfl_xor(acc[k], off);
         if (g == 0) {
-            float *sp = t.s_out + (int64_t)(rp.out_row0 + ci) * t.lds + sub * VEC;
+            float *sp = t.s_out + (int64_t)(rp.out_row0 + c0 + i) * t.lds + sub * VEC;
 #pragma unroll
-            for (int i = 0; i < VEC; i += 4)
-                *reinterpret_cast<float4 *>(sp + i) =
-                    make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
+            for (int k = 0; k < VEC; k += 4)
+                *reinterpret_cast<float4 *>(sp + k) =
+                    make_float4(acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
         }
+        col = ncol;
+        val = nval;
     }
 }
 

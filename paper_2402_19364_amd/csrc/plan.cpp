@@ -274,21 +274,84 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         }
     p.n_up = (int64_t)up.size();
 
-    // chunks: level-0 chunked rows, then chunked upper rows
+    // chunks: level-0 chunked rows, then chunked upper rows.  A row with at
+    // least kWindowRow far entries (beyond the head columns and the band
+    // around the row's own level-0 position) splits into a local group and
+    // one group per column window of its far entries; any other long row is
+    // one group.  Each group is cut into chunks of at most kChunk entries,
+    // ascending column within a group.  The windows split the far entries of
+    // the split rows into kChunkWindows ranges of level-0 columns with equal
+    // entry counts.
+    auto is_far = [&](int64_t c, int64_t r0) { return c >= b && std::llabs(c - r0) > b; };
+    auto far_count = [&](const Level &L, int64_t q, bool map, int64_t r0) {
+        int64_t nf = 0;
+        for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e)
+            nf += is_far(map ? pos0[L.vop[L.col[e]]] : L.col[e], r0);
+        return nf;
+    };
+    std::vector<int64_t> win_lo(kChunkWindows + 1, n);  // window w: [win_lo[w], win_lo[w+1])
+    {
+        std::vector<int64_t> cnt(n + 1, 0);
+        int64_t tot = 0;
+        auto count_far = [&](const Level &L, int64_t q, bool map, int64_t r0) {
+            const int64_t nf = far_count(L, q, map, r0);
+            if (nf < kWindowRow) return;
+            for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e) {
+                const int64_t c = map ? pos0[L.vop[L.col[e]]] : L.col[e];
+                if (is_far(c, r0)) ++cnt[c + 1];
+            }
+            tot += nf;
+        };
+        for (int64_t r = 0; r < n; ++r)
+            if (chunked0[r]) count_far(L0, r, false, r);
+        for (int64_t si = 0; si < (int64_t)vrows.size(); ++si)
+            if (!fused[si] && up_len(vrows[si]) > kLongRow) {
+                const Level &L = d.levels[vrows[si].level];
+                count_far(L, vrows[si].pos, true, pos0[L.vop[vrows[si].pos]]);
+            }
+        for (int64_t c = 0; c < n; ++c) cnt[c + 1] += cnt[c];
+        win_lo[0] = 0;
+        int64_t c = 0;
+        for (int w = 1; w < kChunkWindows; ++w) {
+            const int64_t target = (tot * w + kChunkWindows - 1) / kChunkWindows;
+            while (c < n && cnt[c] < target) ++c;
+            win_lo[w] = c;
+        }
+    }
+    auto window_of = [&](int64_t c) -> int {
+        return (int)(std::upper_bound(win_lo.begin() + 1, win_lo.end() - 1, c) -
+                     (win_lo.begin() + 1));
+    };
     std::vector<int32_t> ch_ptr(1, 0), ch_col;
     std::vector<float> ch_val;
+    std::vector<int16_t> ch_group;  // window of a chunk, kChunkWindows = not windowed
     std::vector<int32_t> l0_chunk_first(n, -1), l0_chunk_count(n, 0);
-    auto add_chunks = [&](const Level &L, int64_t q, bool map) -> std::pair<int32_t, int32_t> {
+    std::vector<std::pair<int64_t, int64_t>> ents;  // (group * n + column, entry)
+    auto add_chunks = [&](const Level &L, int64_t q, bool map,
+                          int64_t r0) -> std::pair<int32_t, int32_t> {
         const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
         const int32_t first = (int32_t)(ch_ptr.size() - 1);
-        for (int64_t e = e0; e < e1; e += kChunk) {
-            const int64_t ee = std::min<int64_t>(e + kChunk, e1);
-            for (int64_t j = e; j < ee; ++j) {
-                const int32_t c = L.col[j];
-                ch_col.push_back(map ? pos0[L.vop[c]] : c);
-                ch_val.push_back(L.val[j]);
+        const bool split = far_count(L, q, map, r0) >= kWindowRow;
+        ents.clear();
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t c = map ? pos0[L.vop[L.col[e]]] : L.col[e];
+            const int64_t g = split && is_far(c, r0) ? window_of(c) : kChunkWindows;
+            ents.push_back({g * n + c, e});
+        }
+        std::stable_sort(ents.begin(), ents.end(),
+                         [](const std::pair<int64_t, int64_t> &x,
+                            const std::pair<int64_t, int64_t> &y) { return x.first < y.first; });
+        for (size_t i = 0; i < ents.size();) {
+            const int64_t g = ents[i].first / n;
+            size_t j = i;
+            while (j < ents.size() && j - i < (size_t)kChunk && ents[j].first / n == g) ++j;
+            for (size_t u = i; u < j; ++u) {
+                ch_col.push_back((int32_t)(ents[u].first % n));
+                ch_val.push_back(L.val[ents[u].second]);
             }
             ch_ptr.push_back((int32_t)ch_col.size());
+            ch_group.push_back((int16_t)g);
+            i = j;
         }
         return {first, (int32_t)(ch_ptr.size() - 1) - first};
     };
@@ -303,7 +366,7 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         if (r % rpb0 == 0) far_ptr[blk] = (int32_t)far_col.size();
         const int64_t e0 = L0.row_ptr[r], e1 = L0.row_ptr[r + 1];
         if (chunked0[r]) {
-            auto fc = add_chunks(L0, r, false);
+            auto fc = add_chunks(L0, r, false, r);
             l0_chunk_first[r] = fc.first;
             l0_chunk_count[r] = fc.second;
             ++p.chunked_rows;
@@ -353,7 +416,7 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         const int64_t q = up[s].pos;
         const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
         if (e1 - e0 > kLongRow) {
-            up_chunks[s] = add_chunks(L, q, true);
+            up_chunks[s] = add_chunks(L, q, true, pos0[L.vop[q]]);
             ++p.chunked_rows;
         } else {
             for (int64_t e = e0; e < e1; ++e) {
@@ -366,34 +429,59 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         up_ptr[s + 1] = (int32_t)up_val.size();
     }
     p.n_chunks = (int64_t)ch_ptr.size() - 1;
-    // Run the chunks in order of their first column, not row by row: the hub
-    // rows' chunks that cover the same stretch of columns then run together,
-    // so their X gathers share the caches.  Only
-    // the storage moves: chunk c's partial row sits at n_up + chunk_slot[c]
-    // and every list keeps its order, so the sums are unchanged.
+    // Chunk placement.  Workgroup w of the chunk pass runs on XCD w % kXcds
+    // (dispatch is round-robin over the XCDs) and takes kChunksPerBlock
+    // consecutive chunk slots (a unit).  XCD x gets the units of the windows
+    // w = x, x + kXcds, ... (in that order), then every kXcds-th unit of the
+    // other chunks, so each XCD's L2 holds the hot X rows of its own windows.
+    // Within a group the chunks run in order of their first column.  Slots an
+    // XCD does not fill stay empty (no entries, no partial row).  Only the
+    // storage moves: chunk c's partial row sits at n_up + chunk_slot[c] and
+    // every list keeps its order, so the sums do not depend on the placement.
     std::vector<int32_t> chunk_slot(p.n_chunks);
     {
-        std::vector<int32_t> order_c(p.n_chunks);
-        for (int64_t c = 0; c < p.n_chunks; ++c) order_c[c] = (int32_t)c;
-        std::stable_sort(order_c.begin(), order_c.end(), [&](int32_t x, int32_t y) {
-            return ch_col[ch_ptr[x]] < ch_col[ch_ptr[y]];
-        });
-        std::vector<int32_t> nptr(1, 0), ncol;
+        std::vector<std::vector<int32_t>> grp(kChunkWindows + 1);
+        for (int64_t c = 0; c < p.n_chunks; ++c) grp[ch_group[c]].push_back((int32_t)c);
+        for (auto &g : grp)
+            std::stable_sort(g.begin(), g.end(), [&](int32_t x, int32_t y) {
+                return ch_col[ch_ptr[x]] < ch_col[ch_ptr[y]];
+            });
+        constexpr int U = kChunksPerBlock;
+        std::vector<std::vector<std::pair<size_t, int>>> xcd_units(kXcds);  // (group, first)
+        for (int w = 0; w <= kChunkWindows; ++w)
+            for (size_t i = 0; i < grp[w].size(); i += U) {
+                const int x = w < kChunkWindows ? w % kXcds : (int)((i / U) % kXcds);
+                xcd_units[x].push_back({(size_t)w, (int)i});
+            }
+        size_t per_xcd = 0;
+        for (auto &v : xcd_units) per_xcd = std::max(per_xcd, v.size());
+        p.ch_slots = (int64_t)per_xcd * kXcds * U;
+        std::vector<int32_t> slot_chunk(p.ch_slots, -1);
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t j = 0; j < xcd_units[x].size(); ++j) {
+                const std::vector<int32_t> &g = grp[xcd_units[x][j].first];
+                const size_t i0 = (size_t)xcd_units[x][j].second;
+                for (size_t i = i0; i < std::min(g.size(), i0 + U); ++i)
+                    slot_chunk[(j * kXcds + x) * U + (i - i0)] = g[i];
+            }
+        std::vector<int32_t> nptr(p.ch_slots + 1, 0), ncol;
         std::vector<float> nval;
         ncol.reserve(ch_col.size());
         nval.reserve(ch_val.size());
-        for (int64_t slot = 0; slot < p.n_chunks; ++slot) {
-            const int32_t c = order_c[slot];
-            chunk_slot[c] = (int32_t)slot;
-            ncol.insert(ncol.end(), ch_col.begin() + ch_ptr[c], ch_col.begin() + ch_ptr[c + 1]);
-            nval.insert(nval.end(), ch_val.begin() + ch_ptr[c], ch_val.begin() + ch_ptr[c + 1]);
-            nptr.push_back((int32_t)ncol.size());
+        for (int64_t slot = 0; slot < p.ch_slots; ++slot) {
+            const int32_t c = slot_chunk[slot];
+            if (c >= 0) {
+                chunk_slot[c] = (int32_t)slot;
+                ncol.insert(ncol.end(), ch_col.begin() + ch_ptr[c], ch_col.begin() + ch_ptr[c + 1]);
+                nval.insert(nval.end(), ch_val.begin() + ch_ptr[c], ch_val.begin() + ch_ptr[c + 1]);
+            }
+            nptr[slot + 1] = (int32_t)ncol.size();
         }
         ch_ptr.swap(nptr);
         ch_col.swap(ncol);
         ch_val.swap(nval);
     }
-    p.s_rows = p.n_up + p.n_chunks;
+    p.s_rows = p.n_up + p.ch_slots;
     for (int32_t c : ch_col) seen_ch[c] = 1;
     // partial rows listed by the upper rows: their own chunks
     for (int64_t s = 0; s < p.n_up; ++s) {
@@ -595,7 +683,7 @@ arrow_status_t spmm_group(Plan &p, const OpState *ops, int nops, void *const *ws
     const int64_t nb = final_parts(p, dtype);
 
     RowPass ch{};
-    set_geometry(ch, p.n_chunks, kChunksPerBlock, 1);
+    set_geometry(ch, p.ch_slots, kChunksPerBlock, 1);
     ch.ptr = p.ch_ptr;
     ch.idx = p.ch_col;
     ch.val = p.ch_val;
@@ -716,7 +804,7 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
     switch (kernel) {
     case ARROW_KERNEL_CHUNKS:
         if (p.n_chunks == 0) return 0;
-        return p.ch_nnz * 8 + (p.n_chunks + 1) * 4 + p.distinct_ch * k * sx + p.n_chunks * k * 4;
+        return p.ch_nnz * 8 + (p.ch_slots + 1) * 4 + p.distinct_ch * k * sx + p.n_chunks * k * 4;
     case ARROW_KERNEL_UPPER:
         if (p.n_up == 0) return 0;
         return p.up_nnz * 8 + (p.n_up + 1) * 8 + (p.up_order ? p.n_up : 0) +

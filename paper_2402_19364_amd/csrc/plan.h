@@ -18,7 +18,18 @@ constexpr int kBlocksPerWg = 1;                    // blocks walked by one workg
 // Blocks walked by one workgroup of the level-0 pass of the scaled formats
 // (FP16, FP8), whose prologue also derives the per-column output scales.
 constexpr int kBlocksPerWgScaled = 1;
-constexpr int kChunksPerBlock = 4;                // chunks per workgroup (one per wave)
+constexpr int kChunksPerBlock = kChunksPerWave * 4;  // chunks per workgroup of the chunk pass
+// Column windows of the chunk pass's far entries (a multiple of kXcds).
+#ifndef ARROW_CHUNK_WINDOWS
+#define ARROW_CHUNK_WINDOWS 8
+#endif
+constexpr int kChunkWindows = ARROW_CHUNK_WINDOWS;
+static_assert(kChunkWindows % kXcds == 0, "chunk windows");
+// Rows with at least this many far entries are split by column window.
+#ifndef ARROW_WINDOW_ROW
+#define ARROW_WINDOW_ROW 256
+#endif
+constexpr int kWindowRow = ARROW_WINDOW_ROW;
 
 struct ProfRec {
     int kernel;
@@ -68,6 +79,7 @@ struct Plan {
     int64_t up_nnz = 0, up_ncontrib = 0;
     // chunk pass
     int64_t n_chunks = 0, chunked_rows = 0;
+    int64_t ch_slots = 0;  // chunk slots (a multiple of kXcds * kChunksPerBlock; some empty)
     int32_t *ch_ptr = nullptr, *ch_col = nullptr;
     float *ch_val = nullptr;
     int64_t ch_nnz = 0;
@@ -78,7 +90,7 @@ struct Plan {
     int32_t up_batch = kBatchWide, l0_batch = kBatchWide;
     int32_t up_batch_auto = kBatchWide, l0_batch_auto = kBatchWide;
 
-    int64_t s_rows = 0;  // partial-row buffer rows = n_up + n_chunks
+    int64_t s_rows = 0;  // partial-row buffer rows = n_up + ch_slots
     // distinct X rows each pass reads (algorithmic byte model)
     int64_t distinct_l0 = 0, distinct_up = 0, distinct_ch = 0;
 
