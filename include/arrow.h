@@ -75,7 +75,8 @@ enum {
 typedef int32_t arrow_la_t;
 enum {
     ARROW_LA_RANDOM_FOREST = 0, /* random spanning forest + smallest-first order (Sections 5.3-5.4) */
-    ARROW_LA_IDENTITY = 1       /* vertices in id order (the input's own ordering) */
+    ARROW_LA_IDENTITY = 1,      /* vertices in id order (the input's own ordering) */
+    ARROW_LA_SEPARATOR = 2      /* recursive separators (Section 5.2): BFS-level separators */
 };
 
 typedef struct arrow_decomp_s *arrow_decomp_t; /* host object */

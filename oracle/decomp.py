@@ -22,8 +22,9 @@ of Fig. 3):
    Eq. (1) and the storage lemma of Section 6.2).
 
 Reference LA-Decompose (Section 5.1) with random spanning forest linear
-arrangements (Section 5.3) and smallest-first tree order (Section 5.4), with
-the readings of the points the paper leaves open:
+arrangements (Section 5.3) and smallest-first tree order (Section 5.4), or
+the separator arrangement (Section 5.2), with the readings of the points the
+paper leaves open:
 
 * degrees are taken in the undirected graph G_i of the symmetrised remaining
   pattern, self loops excluded;
@@ -37,6 +38,12 @@ the readings of the points the paper leaves open:
 * trees follow the head in decreasing size, ties by root id; trees of one
   vertex that still hold entries (to the head) come next, then vertices
   without entries, each group by id;
+* separator arrangement: components in increasing size (ties by smallest
+  id); the separator of a connected set is the first BFS level (from a
+  pseudo-peripheral vertex: the last vertex reached by a BFS from the
+  smallest id) at which the BFS has reached half of the set; BFS visits
+  neighbours by id; vertices without edges in G'_i follow as for the
+  forest;
 * an entry (u, v) goes to B_i when its positions satisfy the arrow predicate,
   otherwise to A_{i+1};
 * the loop runs while nnz(A_i) > 2b counted on the symmetrised pattern; the
@@ -321,6 +328,98 @@ def random_forest_arrangement(n, verts_mask, eu, ev, seed, level):
     return tree_order, singles
 
 
+def _components(vertices, adj, alive):
+    """Connected components of the subgraph induced on `vertices` (alive),
+    each a list in BFS order from its smallest vertex (neighbours by id)."""
+    seen = set()
+    comps = []
+    for v0 in sorted(vertices):
+        if v0 in seen:
+            continue
+        seen.add(v0)
+        comp = [v0]
+        for v in comp:
+            for w in adj[v]:
+                if alive[w] and w not in seen:
+                    seen.add(w)
+                    comp.append(w)
+        comps.append(comp)
+    return comps
+
+
+def _bfs_levels(start, adj, alive):
+    """BFS levels from `start` inside the alive vertices (neighbours by id)."""
+    levels = [[start]]
+    seen = {start}
+    while True:
+        nxt = []
+        for v in levels[-1]:
+            for w in adj[v]:
+                if alive[w] and w not in seen:
+                    seen.add(w)
+                    nxt.append(w)
+        if not nxt:
+            return levels
+        levels.append(nxt)
+
+
+def separator_arrangement(n, verts_mask, eu, ev):
+    """Separator-LA (Section 5.2) of the graph on the vertices where verts_mask
+    is true.  A vertex set is arranged as: its connected components in
+    increasing size (ties by smallest id), each arranged recursively; a
+    connected set places a separator S first and then arranges the rest.  S
+    is a level of a BFS level structure: start at the smallest vertex, restart
+    from the last vertex that BFS reaches (a pseudo-peripheral vertex), and
+    take the first level at which the BFS from there has reached at least
+    half of the set.  Returns (order of the vertices in components of >= 2
+    vertices, singleton vertices), like the random-forest arrangement."""
+    adj = {}
+    for a, c in zip(eu.tolist(), ev.tolist()):
+        adj.setdefault(a, []).append(c)
+        adj.setdefault(c, []).append(a)
+    for v in adj:
+        adj[v].sort()
+    if not adj:
+        return [], np.flatnonzero(verts_mask)
+    alive = np.zeros(n, dtype=bool)
+    alive[list(adj)] = True
+    order = []
+    # work items: ("set", vertices) arranges a set, ("place", vertices) emits
+    stack = [("set", sorted(adj))]
+    while stack:
+        kind, vs = stack.pop()
+        if kind == "place":
+            order.extend(vs)
+            continue
+        comps = _components(vs, adj, alive)
+        if len(comps) > 1:
+            comps.sort(key=lambda cc: (len(cc), min(cc)))
+            for cc in reversed(comps):
+                stack.append(("set", cc))
+            continue
+        comp = comps[0]
+        if len(comp) == 1:
+            order.append(comp[0])
+            alive[comp[0]] = False
+            continue
+        last = _bfs_levels(min(comp), adj, alive)[-1][-1]
+        levels = _bfs_levels(last, adj, alive)
+        reached = 0
+        for lev in levels:
+            reached += len(lev)
+            if 2 * reached >= len(comp):
+                sep = lev
+                break
+        for v in sep:
+            alive[v] = False
+        rest = [v for v in comp if alive[v]]
+        if rest:
+            stack.append(("set", rest))
+        stack.append(("place", sep))
+    singles = np.flatnonzero(verts_mask & ~np.isin(np.arange(n), np.asarray(order, dtype=np.int64)))
+    return order, singles
+
+
 def la_decompose(csr, b: int, seed: int = 0, la: str = "random_forest", trace=None):
     """Reference LA-Decompose.  Returns the list of levels (see module doc).
 
@@ -361,6 +460,9 @@ def la_decompose(csr, b: int, seed: int = 0, la: str = "random_forest", trace=No
             if la == "random_forest":
                 tree_order, singles = random_forest_arrangement(
                     n, ~is_head & has_entry, eu[keep_e], ev[keep_e], seed, level)
+            elif la == "separator":
+                tree_order, singles = separator_arrangement(
+                    n, ~is_head & has_entry, eu[keep_e], ev[keep_e])
             elif la == "identity":
                 tree_order, singles = [], np.flatnonzero(~is_head & has_entry)
             else:

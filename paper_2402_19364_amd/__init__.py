@@ -9,6 +9,7 @@ Communication-Efficient Sparse Matrix Multiplication", PPoPP 2024.
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import os
 from typing import Optional, Sequence
 
@@ -19,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libarrow.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_IO, ERR_INTERNAL = range(7)
 F32, F16, BF16, F8E4M3 = 0, 1, 2, 3
-LA_RANDOM_FOREST, LA_IDENTITY = 0, 1
+LA_RANDOM_FOREST, LA_IDENTITY, LA_SEPARATOR = 0, 1, 2
 KERNEL_CHUNKS, KERNEL_UPPER, KERNEL_LEVEL0, KERNEL_NORM, KERNEL_PERMUTE = range(5)
 KERNEL_NAMES = {KERNEL_CHUNKS: "chunks", KERNEL_UPPER: "upper", KERNEL_LEVEL0: "level0",
                 KERNEL_NORM: "norm", KERNEL_PERMUTE: "permute"}
@@ -181,6 +182,7 @@ class Decomposition:
 
     def __init__(self, handle: int):
         self._h = ctypes.c_void_p(handle)
+        self.from_cache = False
 
     @classmethod
     def from_csr(cls, n: int, row_ptr, col, val, b: int, seed: int = 0,
@@ -266,6 +268,40 @@ class Decomposition:
             self.close()
         except Exception:
             pass
+
+
+def decompose_cached(n: int, row_ptr, col, val, b: int, cache_dir: str, seed: int = 0,
+                     la: int = LA_RANDOM_FOREST, max_levels: int = 0,
+                     threads: int = 0) -> "Decomposition":
+    """Decomposition of a CSR matrix through an on-disk cache (serving cold
+    starts): the file is named by a SHA-256 of the matrix and the options, is
+    written with arrow_decomp_save on a miss and read with arrow_decomp_load on
+    a hit (a file that fails to load is recomputed and replaced).  The thread
+    count is not part of the key: the decomposition does not depend on it.
+    The returned object's `from_cache` tells which happened."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.float32)
+    h = hashlib.sha256()
+    h.update(np.array([1, n, b, seed & ((1 << 64) - 1), la, max_levels],
+                      dtype=np.uint64).tobytes())
+    for a in (rp, c, v):
+        h.update(a.tobytes())
+    os.makedirs(cache_dir, exist_ok=True)
+    path = os.path.join(cache_dir, h.hexdigest()[:40] + ".arrowdec")
+    if os.path.exists(path):
+        try:
+            d = Decomposition.load(path)
+            d.from_cache = True
+            return d
+        except ArrowError:
+            pass
+    d = Decomposition.from_csr(n, rp, c, v, b, seed, la, max_levels, threads)
+    tmp = f"{path}.tmp{os.getpid()}"
+    d.save(tmp)
+    os.replace(tmp, path)
+    d.from_cache = False
+    return d
 
 
 # ---------------------------------------------------------------------------

@@ -1,5 +1,6 @@
 // Host LA-Decompose (Section 5.1) with the random spanning forest linear
-// arrangement (Section 5.3) and smallest-first tree order (Section 5.4).
+// arrangement (Section 5.3) and smallest-first tree order (Section 5.4), or
+// the separator arrangement (Section 5.2, layout_separator).
 //
 // Per level i, on the undirected graph G_i of the symmetrised remaining
 // pattern (self loops excluded):
@@ -189,6 +190,137 @@ void layout_forest(int64_t n, const std::vector<int32_t> &fu, const std::vector<
             order.push_back(v);
             placed[v] = 1;
         }
+}
+
+// Separator arrangement (Section 5.2) of the graph with edges (fu, fv):
+// a vertex set is laid out as its connected components in increasing size
+// (ties: smaller smallest id), each recursively; a connected set places a
+// separator S first and then lays out the rest.  S is the first level of a
+// BFS level structure rooted at a pseudo-peripheral vertex (the last vertex
+// reached by a BFS from the set's smallest id) at which the BFS has reached
+// at least half of the set.  BFS visits neighbours in increasing id.  Appends
+// to `order`, marks `placed`.
+void layout_separator(int64_t n, const std::vector<int32_t> &fu, const std::vector<int32_t> &fv,
+                      std::vector<int32_t> &order, std::vector<uint8_t> &placed) {
+    const size_t m = fu.size();
+    if (m == 0) return;
+    std::vector<int64_t> aptr(n + 1, 0);
+    for (size_t e = 0; e < m; ++e) {
+        ++aptr[fu[e] + 1];
+        ++aptr[fv[e] + 1];
+    }
+    for (int64_t i = 0; i < n; ++i) aptr[i + 1] += aptr[i];
+    std::vector<int32_t> adj(2 * m);
+    {
+        std::vector<int64_t> fill(aptr.begin(), aptr.end() - 1);
+        for (size_t e = 0; e < m; ++e) {
+            adj[fill[fu[e]]++] = fv[e];
+            adj[fill[fv[e]]++] = fu[e];
+        }
+    }
+    std::vector<uint8_t> alive(n, 0);
+    std::vector<int32_t> top;
+    for (int64_t v = 0; v < n; ++v)
+        if (aptr[v + 1] > aptr[v]) {
+            std::sort(adj.begin() + aptr[v], adj.begin() + aptr[v + 1]);
+            alive[v] = 1;
+            top.push_back((int32_t)v);
+        }
+    std::vector<int32_t> stamp(n, 0);  // visit marks: stamp[v] == cur
+    int32_t cur = 0;
+    // BFS inside the alive vertices from `start`; `out` gets the visit order,
+    // `lev` the offsets of the levels in it
+    std::vector<int32_t> bfs;
+    std::vector<int64_t> lev;
+    auto bfs_levels = [&](int32_t start) {
+        ++cur;
+        bfs.clear();
+        lev.clear();
+        bfs.push_back(start);
+        stamp[start] = cur;
+        lev.push_back(0);
+        size_t h = 0;
+        while (h < bfs.size()) {
+            const size_t end = bfs.size();
+            lev.push_back((int64_t)end);
+            for (; h < end; ++h) {
+                const int32_t v = bfs[h];
+                for (int64_t a = aptr[v]; a < aptr[v + 1]; ++a) {
+                    const int32_t w = adj[a];
+                    if (alive[w] && stamp[w] != cur) {
+                        stamp[w] = cur;
+                        bfs.push_back(w);
+                    }
+                }
+            }
+        }
+        // lev[i] .. lev[i+1]: level i (the last entry equals bfs.size())
+    };
+    struct Item {
+        bool place;
+        std::vector<int32_t> vs;
+    };
+    std::vector<Item> stack;
+    stack.push_back({false, std::move(top)});
+    std::vector<std::vector<int32_t>> comps;
+    while (!stack.empty()) {
+        Item it = std::move(stack.back());
+        stack.pop_back();
+        if (it.place) {
+            for (int32_t v : it.vs) {
+                order.push_back(v);
+                placed[v] = 1;
+            }
+            continue;
+        }
+        // connected components of the set, seeds in increasing id
+        std::sort(it.vs.begin(), it.vs.end());
+        ++cur;
+        comps.clear();
+        for (int32_t v0 : it.vs) {
+            if (stamp[v0] == cur) continue;
+            stamp[v0] = cur;
+            std::vector<int32_t> comp(1, v0);
+            for (size_t h = 0; h < comp.size(); ++h) {
+                const int32_t v = comp[h];
+                for (int64_t a = aptr[v]; a < aptr[v + 1]; ++a) {
+                    const int32_t w = adj[a];
+                    if (alive[w] && stamp[w] != cur) {
+                        stamp[w] = cur;
+                        comp.push_back(w);
+                    }
+                }
+            }
+            comps.push_back(std::move(comp));
+        }
+        if (comps.size() > 1) {
+            // comp[0] is each component's smallest id
+            std::stable_sort(comps.begin(), comps.end(),
+                             [](const std::vector<int32_t> &a, const std::vector<int32_t> &b) {
+                                 return a.size() != b.size() ? a.size() < b.size() : a[0] < b[0];
+                             });
+            for (size_t j = comps.size(); j-- > 0;) stack.push_back({false, std::move(comps[j])});
+            continue;
+        }
+        std::vector<int32_t> comp = std::move(comps[0]);
+        if (comp.size() == 1) {
+            order.push_back(comp[0]);
+            placed[comp[0]] = 1;
+            alive[comp[0]] = 0;
+            continue;
+        }
+        bfs_levels(comp[0]);
+        bfs_levels(bfs.back());
+        size_t li = 0;
+        while (2 * (size_t)lev[li + 1] < comp.size()) ++li;
+        std::vector<int32_t> sep(bfs.begin() + lev[li], bfs.begin() + lev[li + 1]);
+        for (int32_t v : sep) alive[v] = 0;
+        std::vector<int32_t> rest;
+        for (int32_t v : comp)
+            if (alive[v]) rest.push_back(v);
+        if (!rest.empty()) stack.push_back({false, std::move(rest)});
+        stack.push_back({true, std::move(sep)});
+    }
 }
 
 // Greedy vertex cover of a small edge set: repeatedly the vertex with the
@@ -495,7 +627,8 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
         set_error("threads must be >= 0 (0 = every hardware thread)");
         return ARROW_ERR_INVALID_ARG;
     }
-    if (opts.la != ARROW_LA_RANDOM_FOREST && opts.la != ARROW_LA_IDENTITY) {
+    if (opts.la != ARROW_LA_RANDOM_FOREST && opts.la != ARROW_LA_IDENTITY &&
+        opts.la != ARROW_LA_SEPARATOR) {
         set_error("unknown linear arrangement kind");
         return ARROW_ERR_INVALID_ARG;
     }
@@ -642,6 +775,15 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
                 std::vector<int32_t> fu, fv;
                 boruvka_msf(nt, n, eu, ev, key, std::move(live), fu, fv);
                 layout_forest(n, fu, fv, order, placed);
+            } else if (opts.la == ARROW_LA_SEPARATOR) {
+                // the edges of G_i - H_i
+                std::vector<int32_t> gu, gv;
+                for (int64_t e = 0; e < ne; ++e)
+                    if (!is_head[eu[e]] && !is_head[ev[e]]) {
+                        gu.push_back(eu[e]);
+                        gv.push_back(ev[e]);
+                    }
+                layout_separator(n, gu, gv, order, placed);
             }
         }
         for (int64_t v = 0; v < n; ++v)

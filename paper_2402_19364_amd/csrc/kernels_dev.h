@@ -254,12 +254,20 @@ __device__ __forceinline__ float pow2_ceil(double x) {
     return (float)ldexp(1.0, e);
 }
 
-// Workgroup -> row block: workgroup w takes block w.  Dispatch places
-// workgroup w on XCD w % 8, so the eight XCDs work on one narrow stretch of
-// consecutive blocks at a time and share its band window of X through the
-// Infinity Cache; giving each XCD a contiguous range of its own instead
-// measured slower (3% on a 2048^2 grid, 17% on R-MAT 2^22).
-__device__ __forceinline__ int row_block(int bid) { return bid; }
+// Workgroup -> slot (block group) of the row passes.  Dispatch sends
+// workgroup i to XCD i % kXcds; the j-th workgroup of XCD x takes slot
+// row_slot(x, j), so each XCD walks stretches of kXcdSpan consecutive slots
+// (its L2 keeps the band rows the stretch's blocks share) while the eight
+// XCDs stay within one window of 8 * kXcdSpan slots (they share the band
+// window through the Infinity Cache).  The grid is padded to a multiple of
+// 8 * kXcdSpan workgroups per tile; slots past the pass's end exit at once.
+#ifndef ARROW_XCD_SPAN
+#define ARROW_XCD_SPAN 1
+#endif
+constexpr int kXcdSpan = ARROW_XCD_SPAN;
+__device__ __forceinline__ int row_slot(int x, int j) {
+    return (j / kXcdSpan) * (kXcds * kXcdSpan) + x * kXcdSpan + j % kXcdSpan;
+}
 
 // ---------------------------------------------------------------------------
 // row kernel
@@ -280,16 +288,20 @@ constexpr int row_waves_hint() {
     return DT == kF32 && FINAL && !CONTRIB && BATCH != kBatchWide && BATCH <= 5 ? 7 : 1;
 }
 // A launch covers the column tiles of several operands (same storage type
-// and tile width): workgroup i takes tile i % n of block i / n, so the n
-// workgroups of one block run next to each other and the block's matrix
-// entries come from HBM once for all operands (requests on one graph batched
-// into a wider k).  Each tile sees the workgroup partition and the sums of a
-// launch with that tile alone.
+// and tile width): the n workgroups of one slot (one per tile) run on the
+// same XCD, so the block's matrix entries come from HBM once for all
+// operands (requests on one graph batched into a wider k).  Each tile sees
+// the workgroup partition and the sums of a launch with that tile alone.
 template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((
     amdgpu_waves_per_eu(row_waves_hint<DT, CONTRIB, FINAL, BATCH>()))) void row_kernel(RowPass rp,
                                                                                          TileSet ts) {
-    const Tile &t = ts.t[blockIdx.x % ts.n];
+    // the n tiles of a slot run on the slot's XCD (see row_slot)
+    const int xcd = blockIdx.x % kXcds;
+    const int rest = blockIdx.x / kXcds;
+    const Tile &t = ts.t[rest % ts.n];
+    const int wg = row_slot(xcd, rest / ts.n);
+    if (wg >= rp.nwg) return;  // grid padding
     using F = Fmt<DT>;
     constexpr int VEC = F::kVec;
     constexpr int LPR = KT / VEC;             // lanes per row
@@ -317,7 +329,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     __shared__ int32_t s_ftab[FAR ? STAGE_FAR : 1];
     __shared__ int32_t s_fb[2];
 
-    const int wg = row_block(blockIdx.x / ts.n);
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave = tid / kWave;
@@ -915,7 +926,11 @@ namespace detail {
 template <int KT, int DT, bool OFF32, int BATCH>
 hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const TileSet &t,
                         hipStream_t s) {
-    dim3 grid((unsigned)((int64_t)rp.nwg * t.n)), block(dev::kBlockThreads);
+    // row passes: whole stretches of 8 * kXcdSpan slots (see row_slot); the
+    // chunk pass's slot count is already a multiple of kXcds
+    const int64_t span = (int64_t)kXcds * (mode == kPassChunk ? 1 : dev::kXcdSpan);
+    const int64_t slots = (rp.nwg + span - 1) / span * span;
+    dim3 grid((unsigned)(slots * t.n)), block(dev::kBlockThreads);
     switch (mode) {
     case kPassChunk:
         hipLaunchKernelGGL((dev::chunk_kernel<KT, DT, OFF32>), grid, block, 0, s, rp, t);

@@ -46,11 +46,15 @@ def _small_graphs():
     return gs
 
 
-@pytest.mark.parametrize("la", [A_.LA_RANDOM_FOREST, A_.LA_IDENTITY])
+_LA_NAMES = {A_.LA_RANDOM_FOREST: "random_forest", A_.LA_IDENTITY: "identity",
+             A_.LA_SEPARATOR: "separator"}
+
+
+@pytest.mark.parametrize("la", [A_.LA_RANDOM_FOREST, A_.LA_IDENTITY, A_.LA_SEPARATOR])
 @pytest.mark.parametrize("b", [2, 3, 8])
 def test_decomposition_matches_oracle_bitwise(la, b):
     for i, A in enumerate(_small_graphs()):
-        ref = D.la_decompose(A, b, seed=17 + i, la="random_forest" if la == 0 else "identity")
+        ref = D.la_decompose(A, b, seed=17 + i, la=_LA_NAMES[la])
         got = _lib_decompose(A, b, seed=17 + i, la=la).levels()
         _assert_same(got, ref)
 
@@ -295,3 +299,42 @@ def test_block_stats_match_a_brute_force_count():
     assert st["nonzero_blocks"] == st["entries"] == st["hist"][9]
     with pytest.raises(A_.ArrowError):
         d.block_stats(0, 0)
+
+
+def test_decompose_cached_roundtrip(tmp_path):
+    """The serving cache: a miss decomposes and writes the file, a hit loads
+    the same levels bit for bit, other options or values miss, and a damaged
+    file is recomputed."""
+    A = W.make_matrix("rmat", 10, "row_normalized", 31, 32, 8)
+    cache = str(tmp_path / "dec")
+    d1 = A_.decompose_cached(A.n, A.row_ptr, A.col, A.val, 32, cache, seed=3)
+    assert not d1.from_cache
+    files = os.listdir(cache)
+    assert len(files) == 1 and files[0].endswith(".arrowdec")
+    d2 = A_.decompose_cached(A.n, A.row_ptr, A.col, A.val, 32, cache, seed=3, threads=4)
+    assert d2.from_cache
+    _assert_same(d2.levels(), d1.levels())
+    d3 = A_.decompose_cached(A.n, A.row_ptr, A.col, A.val, 32, cache, seed=4)
+    assert not d3.from_cache
+    v = A.val.copy()
+    v[0] = np.nextafter(v[0], np.float32(2.0))
+    d4 = A_.decompose_cached(A.n, A.row_ptr, A.col, v, 32, cache, seed=3)
+    assert not d4.from_cache and len(os.listdir(cache)) == 3
+    path = os.path.join(cache, files[0])
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0xFF
+    open(path, "wb").write(bytes(raw))
+    d5 = A_.decompose_cached(A.n, A.row_ptr, A.col, A.val, 32, cache, seed=3)
+    assert not d5.from_cache
+    _assert_same(d5.levels(), d1.levels())
+    assert A_.decompose_cached(A.n, A.row_ptr, A.col, A.val, 32, cache, seed=3).from_cache
+
+
+@pytest.mark.parametrize("graph", [("grid2d", 20, 8), ("grid3d", 8, 8), ("rmat", 11, 32)])
+def test_separator_decomposition_matches_oracle_bitwise(graph):
+    kind, size, b = graph
+    A = W.make_matrix(kind, size, "uniform", 41, 42, 8)
+    ref = D.la_decompose(A, b, seed=9, la="separator")
+    got = _lib_decompose(A, b, seed=9, la=A_.LA_SEPARATOR).levels()
+    _assert_same(got, ref)
+    D.validate(A, got, b)

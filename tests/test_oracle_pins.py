@@ -144,3 +144,89 @@ def test_la_decompose_lemma_counting_step(case, la):
         assert np.array_equal(_remaining_edges(levels, i + 1, n), want), (name, i)
         checked += 1
     assert checked >= 1
+
+
+# ---------------------------------------------------------------------------
+# separator arrangement (Section 5.2): properties fixed by the definition and
+# the bound of Table 1, checked with scipy's connected components
+# ---------------------------------------------------------------------------
+
+def _arrangement(A):
+    eu, ev = D._undirected_edges(A.rows(), np.asarray(A.col, np.int64), A.n)
+    order, singles = D.separator_arrangement(A.n, np.ones(A.n, dtype=bool), eu, ev)
+    pos = np.full(A.n, -1, dtype=np.int64)
+    pos[np.asarray(order, dtype=np.int64)] = np.arange(len(order))
+    return eu, ev, order, singles, pos
+
+
+def _scipy_components(n, eu, ev, keep):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    m = keep[eu] & keep[ev]
+    G = sp.coo_matrix((np.ones(int(m.sum())), (eu[m], ev[m])), shape=(n, n))
+    _, lab = connected_components(G, directed=False)
+    return lab
+
+
+@pytest.mark.parametrize("side", [6, 9, 16, 25])
+def test_separator_top_level_is_a_two_thirds_separator_placed_first(side):
+    """On a connected grid the first vertices placed form a separator S whose
+    removal leaves components of at most 2n/3 vertices; after S every
+    component occupies one contiguous range of positions, in increasing size."""
+    A = W.make_matrix("grid2d", side, "uniform", 0, 1)
+    eu, ev, order, singles, pos = _arrangement(A)
+    n = A.n
+    assert len(order) == n and singles.size == 0 and np.all(pos >= 0)
+    # S = the longest prefix whose removal disconnects what follows, found by
+    # growing the prefix until the rest is disconnected (or empty)
+    for s_len in range(1, n + 1):
+        keep = np.ones(n, dtype=bool)
+        keep[np.asarray(order[:s_len])] = False
+        lab = _scipy_components(n, eu, ev, keep)
+        comps = np.unique(lab[keep])
+        if comps.size >= 2:
+            break
+    sizes = np.array([np.count_nonzero(lab[keep] == c) for c in comps])
+    assert sizes.max() * 3 <= 2 * n
+    # each component contiguous after S, components in increasing size
+    starts = []
+    for c in comps:
+        p = np.sort(pos[np.flatnonzero(keep & (lab == c))])
+        assert p[-1] - p[0] + 1 == p.size
+        starts.append((p[0], p.size))
+    starts.sort()
+    assert starts[0][0] == s_len
+    assert [sz for _, sz in starts] == sorted(sz for _, sz in starts)
+
+
+def test_separator_cost_bounds():
+    """Table 1: planar graphs (2D grids, max degree 4) get an arrangement of
+    cost O(n Delta sqrt(n)) -- the ratio stays below a constant while a random
+    order grows like sqrt(n); a path gets at most n log2 n."""
+    ratios = []
+    for side in (8, 16, 32, 48):
+        A = W.make_matrix("grid2d", side, "uniform", 0, 1)
+        eu, ev, _, _, pos = _arrangement(A)
+        n = A.n
+        lam = np.abs(pos[eu] - pos[ev]).sum()
+        rnd = np.random.default_rng(side).permutation(n)
+        lam_rnd = np.abs(rnd[eu] - rnd[ev]).sum()
+        ratios.append(lam / (n * 4 * math.sqrt(n)))
+        assert lam < lam_rnd
+    assert max(ratios) <= 1.5
+    for n in (64, 256, 1024):
+        lab = np.random.default_rng(n).permutation(n)
+        eu = np.minimum(lab[:-1], lab[1:])
+        ev = np.maximum(lab[:-1], lab[1:])
+        order, singles = D.separator_arrangement(n, np.ones(n, dtype=bool), eu, ev)
+        pos = np.empty(n, dtype=np.int64)
+        pos[np.asarray(order)] = np.arange(n)
+        assert np.abs(pos[eu] - pos[ev]).sum() <= n * math.log2(n)
+
+
+def test_separator_decompositions_are_valid():
+    for A, b in ((W.make_matrix("grid2d", 24, "sym_laplacian", 0, 1), 8),
+                 (W.make_matrix("grid3d", 7, "sym_laplacian", 0, 1), 16),
+                 (W.make_matrix("rmat", 10, "row_normalized", 5, 6, 8), 16),
+                 (W.random_graph(200, 0.02, 4), 4)):
+        D.validate(A, D.la_decompose(A, b, seed=2, la="separator"), b)
