@@ -1,10 +1,13 @@
-"""ORACLE (test infrastructure only): Y = A X in FP64 and its renormalised iteration.
+"""ORACLE (test infrastructure only): Y = A X in FP64, its renormalised
+iteration and the GNN-style step ReLU((A X) W).
 
 Parity status: pinned.  The CSR product is checked against a pure-Python
 triple loop on tiny inputs, against a dense product on small inputs, and
 against closed forms at full size (Laplacian null vector, row-stochastic
 matrices, identity).  The iteration is checked against closed-form power
-iterations (diagonal matrices, path-graph eigenvectors).
+iterations (diagonal matrices, path-graph eigenvectors).  The GNN step is
+checked against pure-Python loops and against permutation and diagonal
+weight matrices, whose products are known column by column.
 """
 from __future__ import annotations
 
@@ -146,6 +149,30 @@ def iterate(csr, X0, T: int):
         Ys.append(Y)
         nus.append(nu)
     return Ys, nus
+
+
+def gnn_layer(csr, X, W) -> np.ndarray:
+    """One step of the GNN-style iteration (Section 2: sigma an element-wise
+    function, here with a k x k weight matrix): Z = ReLU((A X) W) in FP64.
+    A X is the CSR product above; the k x k product is a library matmul."""
+    Y = csr_spmm(csr, X)
+    return np.maximum(Y @ np.asarray(W, dtype=np.float64), 0.0)
+
+
+def gnn_brute_force(csr, X, W) -> list:
+    """Pure-Python loops of ReLU((A X) W) (tiny inputs only)."""
+    Y = brute_force(csr, X)
+    k = len(W)
+    out = []
+    for row in Y:
+        z = []
+        for j in range(k):
+            acc = 0.0
+            for i in range(k):
+                acc += row[i] * float(W[i][j])
+            z.append(acc if acc > 0.0 else 0.0)
+        out.append(z)
+    return out
 
 
 def rel_fro(a, ref) -> float:

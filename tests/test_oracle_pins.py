@@ -230,3 +230,33 @@ def test_separator_decompositions_are_valid():
                  (W.make_matrix("rmat", 10, "row_normalized", 5, 6, 8), 16),
                  (W.random_graph(200, 0.02, 4), 4)):
         D.validate(A, D.la_decompose(A, b, seed=2, la="separator"), b)
+
+
+# ---------------------------------------------------------------------------
+# GNN-style step ReLU((A X) W)
+# ---------------------------------------------------------------------------
+
+def test_gnn_layer_brute_force_and_special_weights():
+    A = W.random_graph(30, 0.15, 7, values="uniform", diagonal=True)
+    rng = np.random.default_rng(8)
+    k = 5
+    X = rng.standard_normal((A.n, k))
+    Wm = rng.standard_normal((k, k))
+    Z = S.gnn_layer(A, X, Wm)
+    ref = np.array(S.gnn_brute_force(A, X.tolist(), Wm.tolist()))
+    assert np.allclose(Z, ref, rtol=1e-12, atol=1e-12)
+    assert np.all(Z >= 0) and np.any(Z > 0) and np.any(Z == 0)
+    Y = S.csr_spmm(A, X)
+    # a permutation matrix moves column j of A X to column perm[j] (a transposed
+    # weight would move it to inv[j] instead)
+    perm = np.array([2, 0, 4, 1, 3])
+    P = np.zeros((k, k))
+    P[np.arange(k), perm] = 1.0
+    Zp = S.gnn_layer(A, X, P)
+    for j in range(k):
+        assert np.array_equal(Zp[:, perm[j]], np.maximum(Y[:, j], 0.0))
+    # a diagonal weight scales each column, ReLU keeps the positive part
+    d = np.array([2.0, -1.0, 0.5, -3.0, 0.0])
+    Zd = S.gnn_layer(A, X, np.diag(d))
+    for j in range(k):
+        assert np.array_equal(Zd[:, j], np.maximum(d[j] * Y[:, j], 0.0))
