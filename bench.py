@@ -242,6 +242,98 @@ def serving_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def gnn_bench(args):
+    """The GNN-style step X_{t+1} = ReLU((A X_t) W) (k x k weights W), T
+    steps on one workload: the fused path (the k x k product, ReLU included,
+    on matrix cores inside the level-0 pass) against the unfused one (the
+    plain product, then a library matmul and ReLU), both in plan order."""
+    import torch
+
+    import paper_2402_19364_amd as arrow
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[args.workload]
+    k = args.k or w.k
+    T = args.iters or w.iters
+    M = W.workload_matrix(w)
+    d = arrow.Decomposition.from_matrix(M, w.b, seed=w.seeds["decompose"])
+    plan = arrow.Plan(d)
+    levels = d.info()["levels"]
+    del d
+    rng = np.random.default_rng(w.seeds["x"] + 1)
+    Wt = torch.from_numpy((rng.standard_normal((k, k)) / np.sqrt(k)).astype(np.float32)).to(dev)
+    x = torch.from_numpy(W.features(M.n, k, w.seeds["x"])).to(dev)
+    xp = plan.empty(k)
+    bufs = [plan.empty(k), plan.empty(k)]
+    z = plan.empty(k)
+    ws = plan.workspace(plan.workspace_size(k))
+
+    def fused():
+        cur = xp
+        for t in range(T):
+            y = bufs[t % 2]
+            plan.spmm([arrow.operand(cur, y, w=Wt)], ws)
+            cur = y
+
+    def unfused():
+        cur = xp
+        for t in range(T):
+            y = bufs[t % 2]
+            plan.spmm([arrow.operand(cur, z)], ws)
+            torch.mm(z, Wt, out=y)
+            torch.relu_(y)
+            cur = y
+
+    plan.permute_in(x, xp)
+    res = {}
+    for name, fn in (("fused", fused), ("unfused", unfused), ("fused2", fused)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(args.steps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        res[name] = ev[0].elapsed_time(ev[1]) / (args.steps * T)
+    # level-0 pass durations (HIP events around every launch): with and
+    # without the epilogue
+    def l0_us(fn):
+        plan.profile(True)
+        fn()
+        torch.cuda.synchronize()
+        plan.profile(False)
+        n_, ms = plan.profile_query(arrow.KERNEL_LEVEL0)
+        return ms / n_ * 1e3
+
+    l0_gnn = l0_us(fused)
+    def plain():
+        cur = xp
+        for t in range(T):
+            plan.spmm([arrow.operand(cur, bufs[t % 2])], ws)
+            cur = bufs[t % 2]
+    l0_plain = l0_us(plain)
+    fused_ms = min(res["fused"], res["fused2"])
+    flops = 2.0 * M.n * k * k
+    line = {
+        "metric": "GNN-style step ReLU((A X) W), k x k product fused into the level-0 pass",
+        "value": round(fused_ms, 4), "unit": "ms per step", "higher_is_better": False,
+        "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": M.n, "nnz": M.nnz, "k": k, "b": w.b,
+                   "steps_per_job": T, "levels": levels},
+        "unfused_ms": round(res["unfused"], 4),
+        "speedup_vs_unfused": round(res["unfused"] / fused_ms, 3),
+        "level0_us": {"with_epilogue": round(l0_gnn, 2), "plain": round(l0_plain, 2)},
+        "epilogue_flops_per_step": flops,
+        "epilogue_TFLOPs_on_added_time": (round(flops / ((l0_gnn - l0_plain) * 1e-6) / 1e12, 1)
+                                          if l0_gnn > l0_plain else None),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +351,8 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run the streaming copy kernel N times over 1 GiB")
     ap.add_argument("--serving", action="store_true", help="run the serving benchmark")
+    ap.add_argument("--gnn", action="store_true",
+                    help="time the GNN-style step ReLU((A X) W) fused and unfused")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-load", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
@@ -282,6 +376,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.serving:
         serving_bench(args)
+        return
+    if args.gnn:
+        gnn_bench(args)
         return
 
     if args.copy_calib:

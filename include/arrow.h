@@ -299,6 +299,12 @@ typedef struct {
     float *y_maxabs;          /* device float[k] out: max |code| of y, or NULL */
     double *y_norm;           /* device double[k] out: ||Y[:, j]||_2 of the stored y, or NULL */
     double *y_inv_norm;       /* device double[k] out: 1/||Y[:, j]||_2 (0 for a zero column), or NULL */
+    const float *w;           /* device float[k*k] row-major, or NULL: the product becomes the
+                                 GNN-style step y = ReLU((A x) w) (Section 2: the iteration with
+                                 an element-wise sigma, here after a k x k weight matrix), fused
+                                 into the last row pass on FP32 matrix cores; F32 only, k one of
+                                 16, 32, 64, 128 (ARROW_ERR_UNSUPPORTED otherwise); y_norm and
+                                 y_inv_norm then describe the stored ReLU output */
 } arrow_operand_t;
 
 /*

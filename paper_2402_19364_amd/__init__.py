@@ -149,7 +149,8 @@ class Operand(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("x_scale", ctypes.c_void_p),
                 ("x_inv_norm", ctypes.c_void_p), ("x_maxabs", ctypes.c_void_p),
                 ("y_scale", ctypes.c_void_p), ("y_maxabs", ctypes.c_void_p),
-                ("y_norm", ctypes.c_void_p), ("y_inv_norm", ctypes.c_void_p)]
+                ("y_norm", ctypes.c_void_p), ("y_inv_norm", ctypes.c_void_p),
+                ("w", ctypes.c_void_p)]
 
 
 def _np_ptr(a: np.ndarray) -> int:
@@ -502,12 +503,16 @@ class Plan:
 
 
 def operand(x, y, dtype="f32", x_scale=None, x_inv_norm=None, x_maxabs=None, y_scale=None,
-            y_maxabs=None, y_norm=None, y_inv_norm=None) -> Operand:
+            y_maxabs=None, y_norm=None, y_inv_norm=None, w=None) -> Operand:
+    """One operand of Plan.spmm.  With `w` (a contiguous k x k FP32 device
+    tensor) the product is the GNN-style step y = ReLU((A x) w)."""
     if tuple(x.shape) != tuple(y.shape):
         raise ValueError("x and y must have the same shape")
+    if w is not None and (tuple(w.shape) != (x.shape[1], x.shape[1]) or not w.is_contiguous()):
+        raise ValueError("w must be a contiguous k x k tensor")
     return Operand(_tptr(x), _tptr(y), x.shape[1], _rows(x, "x"), _rows(y, "y"),
                    _dtype_code(dtype), 0, _tptr(x_scale), _tptr(x_inv_norm), _tptr(x_maxabs),
-                   _tptr(y_scale), _tptr(y_maxabs), _tptr(y_norm), _tptr(y_inv_norm))
+                   _tptr(y_scale), _tptr(y_maxabs), _tptr(y_norm), _tptr(y_inv_norm), _tptr(w))
 
 
 def csr_workspace_size(n: int, k: int) -> int:

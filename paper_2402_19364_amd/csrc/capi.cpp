@@ -524,6 +524,10 @@ static arrow_status_t check_op(const arrow::Plan &P, const arrow_operand_t &o) {
         set_error("y_scale is required for F16 / F8E4M3");
         return ARROW_ERR_INVALID_ARG;
     }
+    if (o.w && (o.dtype != ARROW_F32 || arrow::tile_width(o.k) != o.k)) {
+        set_error("the GNN-style epilogue (w) needs F32 and k in {16, 32, 64, 128}");
+        return ARROW_ERR_UNSUPPORTED;
+    }
     return ARROW_OK;
 }
 
@@ -573,7 +577,7 @@ arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t nu
     for (int32_t i = 0; i < num_ops; ++i) {
         const arrow_operand_t &o = ops[i];
         st[i] = arrow::OpState{o.x, o.y, o.k, o.ldx, o.ldy, o.dtype, o.x_scale, o.x_inv_norm,
-                               o.x_maxabs, o.y_scale, o.y_maxabs, o.y_norm, o.y_inv_norm};
+                               o.x_maxabs, o.y_scale, o.y_maxabs, o.y_norm, o.y_inv_norm, o.w};
         ws[i] = w;
         w += arrow::op_workspace(P, o.k, o.dtype);
     }
@@ -586,7 +590,8 @@ arrow_status_t arrow_spmm(arrow_plan_t p, const arrow_operand_t *ops, int32_t nu
         gws.clear();
         for (int32_t j = i; j < num_ops; ++j)
             if (!done[j] && st[j].dtype == st[i].dtype &&
-                arrow::tile_width(st[j].k) == arrow::tile_width(st[i].k)) {
+                arrow::tile_width(st[j].k) == arrow::tile_width(st[i].k) &&
+                (st[j].w != nullptr) == (st[i].w != nullptr)) {
                 gops.push_back(st[j]);
                 gws.push_back(ws[j]);
                 done[j] = 1;

@@ -77,6 +77,7 @@ struct Tile {
     float *part_max;
     int64_t part_ld;
     float a_inf;
+    const float *w;       // k x k weights of the GNN-style epilogue (row-major), or null
 };
 
 // Column tiles of the operands of one launch (same storage type and tile

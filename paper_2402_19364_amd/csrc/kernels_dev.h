@@ -42,6 +42,7 @@ namespace dev {
 
 constexpr int kWave = 64;
 constexpr int kBlockThreads = 256;
+constexpr int kGnnRows = 16;  // rows of one matrix-core tile of the GNN-style epilogue
 constexpr int kWaves = kBlockThreads / kWave;
 
 // Native clang vectors (the non-temporal builtins need them).
@@ -262,7 +263,7 @@ __device__ __forceinline__ float pow2_ceil(double x) {
 // window through the Infinity Cache).  The grid is padded to a multiple of
 // 8 * kXcdSpan workgroups per tile; slots past the pass's end exit at once.
 #ifndef ARROW_XCD_SPAN
-#define ARROW_XCD_SPAN 1
+#define ARROW_XCD_SPAN 16
 #endif
 constexpr int kXcdSpan = ARROW_XCD_SPAN;
 __device__ __forceinline__ int row_slot(int x, int j) {
@@ -292,7 +293,8 @@ constexpr int row_waves_hint() {
 // same XCD, so the block's matrix entries come from HBM once for all
 // operands (requests on one graph batched into a wider k).  Each tile sees
 // the workgroup partition and the sums of a launch with that tile alone.
-template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR>
+template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR,
+          bool GNN = false>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((
     amdgpu_waves_per_eu(row_waves_hint<DT, CONTRIB, FINAL, BATCH>()))) void row_kernel(RowPass rp,
                                                                                          TileSet ts) {
@@ -358,6 +360,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     __shared__ float s_c[FINAL ? KT : 1];
     __shared__ double s_ssq[FINAL ? kWaves : 1][FINAL ? KT : 1];
     __shared__ float s_max[FINAL ? kWaves : 1][FINAL ? KT : 1];
+    // GNN-style epilogue: each wave stages kGnnRows finished rows (padded
+    // rows: fewer LDS bank conflicts) and their row numbers (-1: none)
+    static_assert(!GNN || (DT == kF32 && FINAL && BATCH == kBatchWide), "GNN epilogue");
+    __shared__ float s_gt[GNN ? kWaves : 1][GNN ? kGnnRows : 1][GNN ? KT + 4 : 1];
+    __shared__ int32_t s_gr[GNN ? kWaves : 1][GNN ? kGnnRows : 1];
     float mul[LDS_SUMS ? 1 : VEC];
     double ssq[LDS_SUMS ? 1 : VEC];
     float cmax[LDS_SUMS ? 1 : VEC];
@@ -390,6 +397,57 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
             }
         }
     }
+
+    // GNN-style epilogue of the wave's staged rows: Z = ReLU(Y W) for a
+    // 16-row tile on matrix cores (16x16x4 FP32 products: lane l holds
+    // A[l % 16][l / 16] and B[l / 16][l % 16], result register q of lane l is
+    // D[4 (l / 16) + q][l % 16]), written back over the tile, then every row
+    // group stores its rows and adds their squares to the wave's column sums.
+    // The first `cnt` slots hold rows (cnt is a multiple of RPW).
+    auto gnn_flush = [&](int cnt) {
+        if constexpr (GNN) {
+            constexpr int NK = KT / 4, NJ = KT / 16;
+            const int li = lane % 16, lk = lane / 16;
+            __builtin_amdgcn_wave_barrier();
+            float a[NK];
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) a[kk] = s_gt[wave][li][4 * kk + lk];
+            const float *wcol = t.w + (int64_t)lk * KT + li;
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb) {
+                float bv[NK];
+#pragma unroll
+                for (int kk = 0; kk < NK; ++kk) bv[kk] = wcol[(int64_t)(4 * kk) * KT + 16 * jb];
+                vf4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kk = 0; kk < NK; ++kk)
+                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], bv[kk], d, 0, 0, 0);
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s_gt[wave][4 * lk + q][16 * jb + li] = fmaxf(d[q], 0.0f);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int sl = g; sl < cnt; sl += RPW) {
+                const int row = s_gr[wave][sl];
+                float v[VEC];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) v[i] = row >= 0 ? s_gt[wave][sl][sub * VEC + i] : 0.0f;
+                if (row >= 0) {
+                    char *yp = reinterpret_cast<char *>(t.y) + (int64_t)row * t.ldy * kElem +
+                               (int64_t)sub * F::kBytes;
+                    F::store(yp, v);
+                }
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    double sq = (double)v[i] * (double)v[i];
+#pragma unroll
+                    for (int off = LPR; off < kWave; off <<= 1) sq += __shfl_xor(sq, off);
+                    if (g == 0) s_ssq[wave][sub * VEC + i] += sq;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    };
 
     for (int bi = 0; bi < rp.blocks_per_wg; ++bi) {
         const int64_t row0 = ((int64_t)wg * rp.blocks_per_wg + bi) * rp.rows_per_block;
@@ -467,6 +525,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
             constexpr bool CSTAGED = decltype(cstaged_tag)::value;
             // wave-uniform trip count: the final pass reduces across the
             // wave's row groups every round (rows past the block end are idle)
+            int gcnt = 0;  // rows staged in the wave's GNN tile
             for (int rbase = wave * RPW; rbase < nr; rbase += RPR) {
                 const int rq = rbase + g;  // slot in the block's processing order
                 const bool live = rq < nr;
@@ -595,7 +654,20 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
                     for (; c1 - c > 2; c += WIDE) batch(c, std::integral_constant<int, WIDE>{});
                     if (c < c1) batch(c, std::integral_constant<int, 2>{});
                 }
-                if constexpr (FINAL && !LDS_SUMS) {
+                if constexpr (FINAL && GNN) {
+                    // stage the scaled row in the wave's tile; a full tile
+                    // (or the wave's last round of the block) goes through
+                    // the k x k product
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i)
+                        s_gt[wave][gcnt + g][sub * VEC + i] = acc[i] * s_mul[sub * VEC + i];
+                    if (sub == 0) s_gr[wave][gcnt + g] = live ? (int)r : -1;
+                    gcnt += RPW;
+                    if (gcnt == kGnnRows || rbase + RPR >= nr) {
+                        gnn_flush(gcnt);
+                        gcnt = 0;
+                    }
+                } else if constexpr (FINAL && !LDS_SUMS) {
                     if (live) {
 #pragma unroll
                         for (int i = 0; i < VEC; ++i) acc[i] = acc[i] * mul[i];
@@ -976,12 +1048,38 @@ hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const TileSet 
     return hipGetLastError();
 }
 
+// The level-0 pass with the GNN-style epilogue (FP32, wide batch).
+template <int KT, int DT, bool OFF32>
+hipError_t launch_gnn(bool code16, const RowPass &rp, const TileSet &t, hipStream_t s) {
+    if constexpr (DT != kF32) {
+        return hipErrorInvalidValue;
+    } else {
+        const int64_t span = (int64_t)kXcds * dev::kXcdSpan;
+        const int64_t slots = (rp.nwg + span - 1) / span * span;
+        dim3 grid((unsigned)(slots * t.n)), block(dev::kBlockThreads);
+        if (code16 && rp.fptr)
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, true, true, true, OFF32, kBatchWide, true, true>), grid,
+                block, 0, s, rp, t);
+        else if (code16)
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, true, true, true, OFF32, kBatchWide, false, true>), grid,
+                block, 0, s, rp, t);
+        else
+            hipLaunchKernelGGL(
+                (dev::row_kernel<KT, DT, false, true, true, OFF32, kBatchWide, false, true>), grid,
+                block, 0, s, rp, t);
+        return hipGetLastError();
+    }
+}
+
 // Short batches are built for 32-bit offsets only (X and the partial-row
 // buffer below 4 GiB); larger operands take the wide batch.
 template <int KT, int DT, bool OFF32>
 hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const TileSet &t,
                         hipStream_t s) {
     if (rp.nwg <= 0) return hipSuccess;
+    if (mode == kPassLevel0 && t.t[0].w) return launch_gnn<KT, DT, OFF32>(code16, rp, t, s);
     if constexpr (OFF32) {
         if (mode != kPassChunk) {
             switch (rp.batch) {

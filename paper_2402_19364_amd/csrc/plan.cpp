@@ -754,6 +754,7 @@ arrow_status_t spmm_group(Plan &p, const OpState *ops, int nops, void *const *ws
             t.part_max = pmax + c0 * nb;
             t.part_ld = nb;
             t.a_inf = (float)p.a_inf;
+            t.w = op.w;  // only with one tile per operand (k = tile width)
             tiles.push_back(t);
         }
     }

@@ -117,6 +117,7 @@ struct OpState {
     float *y_maxabs;
     double *y_norm;
     double *y_inv_norm;
+    const float *w;  // GNN-style epilogue weights (k x k), or null
 };
 
 int64_t elem_size(int dtype);
