@@ -365,9 +365,23 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     static_assert(!GNN || (DT == kF32 && FINAL && BATCH == kBatchWide), "GNN epilogue");
     __shared__ float s_gt[GNN ? kWaves : 1][GNN ? kGnnRows : 1][GNN ? KT + 4 : 1];
     __shared__ int32_t s_gr[GNN ? kWaves : 1][GNN ? kGnnRows : 1];
+    // the k x k weights in matrix-core fragment order (k <= 32; larger k
+    // reads them through the caches, keeping the LDS for occupancy): the four
+    // k-steps 4 kq .. 4 kq + 3 of column
+    // block jb that lane l feeds in are the 16 bytes at ((jb (k/16) + kq) 64
+    // + l) 4, so a lane reads them with one conflict-free 16-byte load
+    constexpr bool WLDS = GNN && KT <= 32;
+    __shared__ float s_w[WLDS ? KT * KT : 1];
     float mul[LDS_SUMS ? 1 : VEC];
     double ssq[LDS_SUMS ? 1 : VEC];
     float cmax[LDS_SUMS ? 1 : VEC];
+    if constexpr (WLDS) {
+        for (int e = tid; e < KT * KT; e += kBlockThreads) {
+            const int j4 = e % 4, l = (e / 4) % kWave, fq = e / (4 * kWave);
+            const int kq = fq % (KT / 16), jb = fq / (KT / 16);
+            s_w[e] = t.w[(int64_t)(16 * kq + 4 * j4 + l / 16) * KT + 16 * jb + l % 16];
+        }
+    }
     if constexpr (FINAL) {
         for (int j = tid; j < KT; j += kBlockThreads) {
             const float xs = t.x_scale ? t.x_scale[j] : 1.0f;
@@ -409,23 +423,41 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
             constexpr int NK = KT / 4, NJ = KT / 16;
             const int li = lane % 16, lk = lane / 16;
             __builtin_amdgcn_wave_barrier();
-            float a[NK];
+            // all NJ column blocks accumulate together over groups of four
+            // k-steps, so every register array is indexed by constants
+            vf4 d[NJ];
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) a[kk] = s_gt[wave][li][4 * kk + lk];
-            const float *wcol = t.w + (int64_t)lk * KT + li;
+            for (int jb = 0; jb < NJ; ++jb) d[jb] = vf4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int kq = 0; kq < NK / 4; ++kq) {
+                float a4[4];
 #pragma unroll
-            for (int jb = 0; jb < NJ; ++jb) {
-                float bv[NK];
+                for (int j = 0; j < 4; ++j) a4[j] = s_gt[wave][li][16 * kq + 4 * j + lk];
 #pragma unroll
-                for (int kk = 0; kk < NK; ++kk) bv[kk] = wcol[(int64_t)(4 * kk) * KT + 16 * jb];
-                vf4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+                for (int jb = 0; jb < NJ; ++jb) {
+                    float b4[4];
+                    if constexpr (WLDS) {
+                        const float4 q4 = *reinterpret_cast<const float4 *>(
+                            &s_w[((jb * (NK / 4) + kq) * kWave + lane) * 4]);
+                        b4[0] = q4.x;
+                        b4[1] = q4.y;
+                        b4[2] = q4.z;
+                        b4[3] = q4.w;
+                    } else {
 #pragma unroll
-                for (int kk = 0; kk < NK; ++kk)
-                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], bv[kk], d, 0, 0, 0);
-                __builtin_amdgcn_wave_barrier();
+                        for (int j = 0; j < 4; ++j)
+                            b4[j] = t.w[(int64_t)(16 * kq + 4 * j + lk) * KT + 16 * jb + li];
+                    }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) s_gt[wave][4 * lk + q][16 * jb + li] = fmaxf(d[q], 0.0f);
+                    for (int j = 0; j < 4; ++j)
+                        d[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], b4[j], d[jb], 0, 0, 0);
+                }
             }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    s_gt[wave][4 * lk + q][16 * jb + li] = fmaxf(d[jb][q], 0.0f);
             __builtin_amdgcn_wave_barrier();
             for (int sl = g; sl < cnt; sl += RPW) {
                 const int row = s_gr[wave][sl];
