@@ -159,6 +159,16 @@ def test_short_batch_chosen_for_stencils():
         _check_trajectory(M, b, 16, 2, la=A_.LA_IDENTITY, label=f"{shape} short batch")
 
 
+def test_separator_arrangement_products():
+    """The product over decompositions built with the separator arrangement
+    (Section 5.2): more levels than the forest on grids, folded and listed
+    rows alike."""
+    for M, b in ((W.make_matrix("grid2d", 48, "sym_laplacian", 81, 82), 48),
+                 (W.make_matrix("grid3d", 14, "sym_laplacian", 83, 84), 196),
+                 (W.make_matrix("rmat", 12, "row_normalized", 85, 86, 16), 64)):
+        _check_trajectory(M, b, 32, 4, la=A_.LA_SEPARATOR, label="separator arrangement")
+
+
 def test_wide_arrow_int32_codes():
     # b > 21845 switches the level-0 pass to 32-bit columns
     M = W.make_matrix("grid2d", 190, "sym_laplacian", 0, 0)
