@@ -224,3 +224,47 @@ def test_full_size_precision_teacher_forced(name, dtype):
     say(f"[full] {name} {dtype} k={k} T={T}: worst teacher-forced {worst:.2e}, drift after "
         f"{T} steps {drift:.2e} (reported, columns {cols})")
     assert np.all(np.isfinite(out.cpu().numpy())) and bool(torch.all(norms > 0))
+
+
+def test_operands_beyond_4_gib_use_64_bit_offsets():
+    """Operands whose rows span 4 GiB or more take the 64-bit-offset kernels
+    (and the wide gather batch): grid2048 with k = 128 columns inside rows of
+    stride 1024 (17 GB per buffer).  Every product equals the one on a
+    contiguous operand (32-bit offsets, the plan's short batch) up to the sign
+    of a zero, and sampled columns match the FP64 oracle within 1e-5."""
+    w, M, plan, vop0 = _plan("grid2048")
+    n, k, ld, T = M.n, 128, 1024, 2
+    X0 = W.features(n, k, 4242)
+    big = [torch.zeros((n, ld), dtype=torch.float32, device="cuda") for _ in range(3)]
+    assert big[0].numel() * 4 >= 1 << 34
+    x_big, y_big = big[0][:, :k], [big[1][:, :k], big[2][:, :k]]
+    x_big.copy_(torch.from_numpy(X0))
+    x_small = torch.from_numpy(X0).cuda()
+    y_small = [plan.empty(k), plan.empty(k)]
+    xp_small = plan.empty(k)
+    xp_big = torch.zeros((n, ld), dtype=torch.float32, device="cuda")[:, :k]
+    plan.permute_in(x_small, xp_small)
+    plan.permute_in(x_big, xp_big)
+    ws = plan.workspace(plan.workspace_size(k))
+    inv = [torch.zeros(k, dtype=torch.float64, device="cuda") for _ in range(4)]
+    cur_s, cur_b = xp_small, xp_big
+    cols = [0, 37, 77, 127]
+    X = X0[:, cols].astype(np.float64)
+    for t in range(T):
+        ops = []
+        for j, (cur, y) in enumerate(((cur_s, y_small[t % 2]), (cur_b, y_big[t % 2]))):
+            plan.spmm([A_.operand(cur, y, x_inv_norm=inv[2 * j + (t - 1) % 2] if t else None,
+                                  y_inv_norm=inv[2 * j + t % 2])], ws)
+        torch.cuda.synchronize()
+        ys, yb = y_small[t % 2], y_big[t % 2]
+        assert torch.equal(ys, yb), t
+        ref = S.csr_spmm(M, X)
+        got = _to_orig(yb[:, cols].cpu().numpy().astype(np.float64), vop0)
+        err = S.rel_fro(got, ref)
+        say(f"[full] grid2048 k={k} ld={ld} t={t}: 64-bit offsets equal the 32-bit run, "
+            f"sampled columns {err:.2e}")
+        assert err <= TOL
+        _, X = S.renormalize(ref)
+        cur_s, cur_b = ys, yb
+    del big, xp_big
+    torch.cuda.empty_cache()
