@@ -380,9 +380,43 @@ std::vector<int32_t> greedy_cover(int64_t n, const std::vector<int32_t> &eu,
 // the others, keyed (c, r), are bucketed by ranges of c (per-thread counts,
 // stable scatter) and each bucket is sorted; the two sorted key lists are
 // then merged per range of u.
+// Undirected edges of a symmetric remaining pattern: the entries above the
+// diagonal, already sorted by (u, v) in CSR order (no duplicates: columns are
+// strictly increasing within a row).
+void upper_edges(int nt, const std::vector<int32_t> &R, const std::vector<int32_t> &C,
+                 std::vector<int32_t> &eu, std::vector<int32_t> &ev, int64_t &n_diag) {
+    const int64_t m = (int64_t)R.size();
+    std::vector<int64_t> c1(nt, 0), cd(nt, 0);
+    par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+        int64_t a = 0, d = 0;
+        for (int64_t e = lo; e < hi; ++e) {
+            a += R[e] < C[e];
+            d += R[e] == C[e];
+        }
+        c1[t] = a, cd[t] = d;
+    });
+    n_diag = 0;
+    for (int t = 0; t < nt; ++t) n_diag += cd[t];
+    const int64_t ne = exclusive_scan(c1);
+    eu.resize(ne);
+    ev.resize(ne);
+    par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+        int64_t o = c1[t];
+        for (int64_t e = lo; e < hi; ++e)
+            if (R[e] < C[e]) {
+                eu[o] = R[e];
+                ev[o] = C[e];
+                ++o;
+            }
+    });
+}
+
+// Undirected edges {u, v} (u < v) of the remaining pattern, sorted and
+// without duplicates, and the number of diagonal entries; `symmetric` (if
+// not null) tells whether the pattern equals its transpose.
 void undirected_edges(int nt, int64_t n, const std::vector<int32_t> &R,
                       const std::vector<int32_t> &C, std::vector<int32_t> &eu,
-                      std::vector<int32_t> &ev, int64_t &n_diag) {
+                      std::vector<int32_t> &ev, int64_t &n_diag, bool *symmetric = nullptr) {
     const int64_t m = (int64_t)R.size();
     const uint64_t un = (uint64_t)std::max<int64_t>(n, 1);
     const int P = 64 * nt;  // buckets of list 2 by ranges of c
@@ -432,6 +466,17 @@ void undirected_edges(int nt, int64_t n, const std::vector<int32_t> &R,
     par_for(nt, P, [&](int64_t lo, int64_t hi, int) {
         for (int64_t q = lo; q < hi; ++q) std::sort(k2.begin() + bstart[q], k2.begin() + bstart[q + 1]);
     });
+    if (symmetric) {
+        // the entries below the diagonal, transposed and sorted, equal the
+        // ones above it exactly when the pattern is symmetric
+        std::vector<uint8_t> same(nt, 1);
+        if (m1 == m2)
+            par_for(nt, m1, [&](int64_t lo, int64_t hi, int t) {
+                for (int64_t i = lo; i < hi && same[t]; ++i) same[t] = k1[i] == k2[i];
+            });
+        *symmetric = m1 == m2;
+        for (int t = 0; t < nt; ++t) *symmetric = *symmetric && same[t];
+    }
     // merge the two sorted lists per range of u, dropping duplicates
     std::vector<int64_t> s1(nt + 1), s2(nt + 1), cnt(nt, 0);
     for (int t = 0; t <= nt; ++t) {
@@ -698,6 +743,7 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
     std::vector<uint8_t> is_head(n), has_entry(n), placed(n);
     std::vector<int32_t> pos(n);
     std::vector<int64_t> tcnt(nt), tcnt2(nt), tmax(nt);
+    bool pattern_symmetric = false;
     for (int32_t level = 0;; ++level) {
         if (opts.max_levels > 0 && level >= opts.max_levels) {
             set_error("decomposition needs more than max_levels = " +
@@ -709,7 +755,14 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
         // undirected edges of the remaining pattern, sorted by (u, v)
         std::vector<int32_t> eu, ev;
         int64_t n_diag = 0;
-        undirected_edges(nt, n, rem.r, rem.c, eu, ev, n_diag);
+        // a symmetric pattern stays symmetric at every level ((u, v) and
+        // (v, u) always land in the same level): its edges are then the
+        // entries above the diagonal, in order
+        if (level > 0 && pattern_symmetric)
+            upper_edges(nt, rem.r, rem.c, eu, ev, n_diag);
+        else
+            undirected_edges(nt, n, rem.r, rem.c, eu, ev, n_diag,
+                             level == 0 ? &pattern_symmetric : nullptr);
         const int64_t ne = (int64_t)eu.size();
         std::fill(has_entry.begin(), has_entry.end(), 0);
         par_for(nt, m, [&](int64_t lo, int64_t hi, int) {
