@@ -47,7 +47,8 @@ def log(*a):
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("kernels.hip", "kernels_dev.h", "kernels_f32.hip", "kernels_bf16.hip",
-              "kernels_f16.hip", "kernels_f8e4m3.hip", "kernels.h", "plan.cpp", "plan.h"):
+              "kernels_f16.hip", "kernels_f8e4m3.hip", "kernels_gnn.hip", "kernels.h", "plan.cpp",
+              "plan.h"):
         with open(os.path.join(ROOT, "paper_2402_19364_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

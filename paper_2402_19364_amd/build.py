@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libarrow.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels_f32.hip", "kernels_bf16.hip", "kernels_f16.hip", "kernels_f8e4m3.hip",
+SOURCES = ["kernels_f32.hip", "kernels_gnn.hip", "kernels_bf16.hip", "kernels_f16.hip", "kernels_f8e4m3.hip",
            "kernels.hip", "static_ws.hip", "plan.cpp", "capi.cpp", "decompose.cpp", "decomp_io.cpp",
            "baseline_rocsparse.cpp"]
 

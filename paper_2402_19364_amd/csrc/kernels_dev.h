@@ -284,9 +284,9 @@ __device__ __forceinline__ int row_slot(int x, int j) {
 // Register target: the FP32 final pass without partial-row lists and with a
 // batch of at most 5 entries fits 72 VGPRs (7 waves per SIMD) without spills
 // when the allocator is asked to; other variants keep the default.
-template <int DT, bool CONTRIB, bool FINAL, int BATCH>
+template <int DT, bool CONTRIB, bool FINAL, int BATCH, bool GNN>
 constexpr int row_waves_hint() {
-    return DT == kF32 && FINAL && !CONTRIB && BATCH != kBatchWide && BATCH <= 5 ? 7 : 1;
+    return DT == kF32 && FINAL && !CONTRIB && BATCH != kBatchWide && BATCH <= 5 && !GNN ? 7 : 1;
 }
 // A launch covers the column tiles of several operands (same storage type
 // and tile width): the n workgroups of one slot (one per tile) run on the
@@ -296,7 +296,7 @@ constexpr int row_waves_hint() {
 template <int KT, int DT, bool CODE16, bool CONTRIB, bool FINAL, bool OFF32, int BATCH, bool FAR,
           bool GNN = false>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((
-    amdgpu_waves_per_eu(row_waves_hint<DT, CONTRIB, FINAL, BATCH>()))) void row_kernel(RowPass rp,
+    amdgpu_waves_per_eu(row_waves_hint<DT, CONTRIB, FINAL, BATCH, GNN>()))) void row_kernel(RowPass rp,
                                                                                          TileSet ts) {
     // the n tiles of a slot run on the slot's XCD (see row_slot)
     const int xcd = blockIdx.x % kXcds;
@@ -362,11 +362,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
     __shared__ float s_max[FINAL ? kWaves : 1][FINAL ? KT : 1];
     // GNN-style epilogue: each wave stages kGnnRows finished rows (padded
     // rows: fewer LDS bank conflicts) and their row numbers (-1: none)
-    static_assert(!GNN || (DT == kF32 && FINAL && BATCH == kBatchWide), "GNN epilogue");
+    static_assert(!GNN || (DT == kF32 && FINAL), "GNN epilogue");
     __shared__ float s_gt[GNN ? kWaves : 1][GNN ? kGnnRows : 1][GNN ? KT + 4 : 1];
     __shared__ int32_t s_gr[GNN ? kWaves : 1][GNN ? kGnnRows : 1];
-    // the k x k weights in matrix-core fragment order (k <= 32; larger k
-    // reads them through the caches, keeping the LDS for occupancy): the four
+    // the k x k weights in matrix-core fragment order (k <= 32, where it
+    // beats reading them through the caches even at one workgroup less per
+    // CU; larger k reads them through the caches, keeping the LDS for
+    // occupancy): the four
     // k-steps 4 kq .. 4 kq + 3 of column
     // block jb that lane l feeds in are the 16 bytes at ((jb (k/16) + kq) 64
     // + l) 4, so a lane reads them with one conflict-free 16-byte load
@@ -472,9 +474,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) {
                     double sq = (double)v[i] * (double)v[i];
+                    if constexpr (LDS_SUMS) {
 #pragma unroll
-                    for (int off = LPR; off < kWave; off <<= 1) sq += __shfl_xor(sq, off);
-                    if (g == 0) s_ssq[wave][sub * VEC + i] += sq;
+                        for (int off = LPR; off < kWave; off <<= 1) sq += __shfl_xor(sq, off);
+                        if (g == 0) s_ssq[wave][sub * VEC + i] += sq;
+                    } else {
+                        ssq[i] += sq;  // the lane's own sums (butterfly at the end)
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -1025,6 +1031,10 @@ __global__ __launch_bounds__(kBlockThreads) void permute_out_kernel(
 // launch templates (instantiated once per storage type)
 // ---------------------------------------------------------------------------
 
+// The level-0 pass with the GNN-style epilogue (FP32; kernels_gnn.hip).
+hipError_t gnn_level0(int kt, bool off32, bool code16, const RowPass &rp, const TileSet &t,
+                      hipStream_t s);
+
 namespace detail {
 
 template <int KT, int DT, bool OFF32, int BATCH>
@@ -1080,38 +1090,14 @@ hipError_t launch_row_b(int mode, bool code16, const RowPass &rp, const TileSet 
     return hipGetLastError();
 }
 
-// The level-0 pass with the GNN-style epilogue (FP32, wide batch).
-template <int KT, int DT, bool OFF32>
-hipError_t launch_gnn(bool code16, const RowPass &rp, const TileSet &t, hipStream_t s) {
-    if constexpr (DT != kF32) {
-        return hipErrorInvalidValue;
-    } else {
-        const int64_t span = (int64_t)kXcds * dev::kXcdSpan;
-        const int64_t slots = (rp.nwg + span - 1) / span * span;
-        dim3 grid((unsigned)(slots * t.n)), block(dev::kBlockThreads);
-        if (code16 && rp.fptr)
-            hipLaunchKernelGGL(
-                (dev::row_kernel<KT, DT, true, true, true, OFF32, kBatchWide, true, true>), grid,
-                block, 0, s, rp, t);
-        else if (code16)
-            hipLaunchKernelGGL(
-                (dev::row_kernel<KT, DT, true, true, true, OFF32, kBatchWide, false, true>), grid,
-                block, 0, s, rp, t);
-        else
-            hipLaunchKernelGGL(
-                (dev::row_kernel<KT, DT, false, true, true, OFF32, kBatchWide, false, true>), grid,
-                block, 0, s, rp, t);
-        return hipGetLastError();
-    }
-}
-
 // Short batches are built for 32-bit offsets only (X and the partial-row
 // buffer below 4 GiB); larger operands take the wide batch.
 template <int KT, int DT, bool OFF32>
 hipError_t launch_row_o(int mode, bool code16, const RowPass &rp, const TileSet &t,
                         hipStream_t s) {
     if (rp.nwg <= 0) return hipSuccess;
-    if (mode == kPassLevel0 && t.t[0].w) return launch_gnn<KT, DT, OFF32>(code16, rp, t, s);
+    if (mode == kPassLevel0 && t.t[0].w)
+        return DT == kF32 ? gnn_level0(KT, OFF32, code16, rp, t, s) : hipErrorInvalidValue;
     if constexpr (OFF32) {
         if (mode != kPassChunk) {
             switch (rp.batch) {
