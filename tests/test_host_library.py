@@ -67,6 +67,22 @@ def test_decomposition_matches_oracle_medium_rmat():
     assert len(got) >= 2
 
 
+def test_nonsymmetric_medium_decomposition_matches_oracle_on_any_thread_count():
+    # a directed R-MAT pattern (each stored entry kept with probability 0.7,
+    # so most edges appear in one direction only) takes the listed-edge path
+    # on several threads; the symmetric path is covered above
+    A = W.make_matrix("rmat", 11, "row_normalized", 31, 32, 16)
+    keep = np.random.default_rng(33).random(A.nnz) < 0.7
+    rows = A.rows()[keep]
+    B = W.from_edges(A.n, np.stack([rows, A.col[keep]], 1), values="uniform", seed=34,
+                     diagonal=True, symmetric=False)
+    assert B.nnz > 8192  # several threads' ranges
+    ref = D.la_decompose(B, 32, seed=6)
+    assert len(ref) >= 2
+    for t in (1, 3, 8):
+        _assert_same(A_.Decomposition.from_matrix(B, 32, seed=6, threads=t).levels(), ref)
+
+
 @pytest.mark.parametrize("cfg", ["grid64"])
 def test_config_small_decomposition(cfg):
     w = W.WORKLOADS[cfg]
