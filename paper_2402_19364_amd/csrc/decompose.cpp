@@ -928,6 +928,25 @@ void forest_from_rows(int nt, int64_t n, const Vec<int64_t> &ptr,
         fv.insert(fv.end(), fv_t[t].begin(), fv_t[t].end());
     }
     jump_to_roots(nt, parent, linked);
+    // the components that have an edge (their roots picked one), numbered
+    // 0 .. nc-1 in root order: the later rounds work on these compact
+    // labels (smaller arrays for their random accesses)
+    Vec<int32_t> cid(n);
+    int64_t nc = 0;
+    {
+        Vec<int64_t> c(nt);
+        par_for(nt, n, [&](int64_t lo, int64_t hi, int t) {
+            int64_t k = 0;
+            for (int64_t v = lo; v < hi; ++v) k += pick[v] >= 0 && parent[v] == v;
+            c[t] = k;
+        });
+        nc = exclusive_scan(c);
+        par_for(nt, n, [&](int64_t lo, int64_t hi, int t) {
+            int32_t k = (int32_t)c[t];
+            for (int64_t v = lo; v < hi; ++v)
+                if (pick[v] >= 0 && parent[v] == v) cid[v] = k++;
+        });
+    }
     Vec<int32_t>().swap(pick);
     // the edges above the diagonal that join two components after round 1,
     // by rows (columns are sorted within a row: the entries above the
@@ -963,8 +982,8 @@ void forest_from_rows(int nt, int64_t n, const Vec<int64_t> &ptr,
             for (int64_t e = upper_begin(v); e < ptr[v + 1]; ++e) {
                 const int32_t w = C[e];
                 if (is_head[w] || parent[w] == pv) continue;
-                cu[o] = pv;
-                cv[o] = parent[w];
+                cu[o] = cid[pv];
+                cv[o] = cid[parent[w]];
                 kk[o] = weight((int32_t)v, w);
                 id[o] = (int32_t)e;
                 ++o;
@@ -972,8 +991,13 @@ void forest_from_rows(int nt, int64_t n, const Vec<int64_t> &ptr,
         }
         seg_n[t] = o - seg_lo[t];
     });
-    Vec<int32_t> chosen;
-    boruvka_rounds(nt, parent, cu, cv, kk, id, seg_lo, seg_n, chosen);
+    Vec<int32_t>().swap(parent);
+    Vec<int32_t>().swap(cid);
+    Vec<int32_t> label(nc), chosen;
+    par_for(nt, nc, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t j = lo; j < hi; ++j) label[j] = (int32_t)j;
+    });
+    boruvka_rounds(nt, label, cu, cv, kk, id, seg_lo, seg_n, chosen);
     for (const int32_t e : chosen) {
         fu.push_back(R[e]);
         fv.push_back(C[e]);
