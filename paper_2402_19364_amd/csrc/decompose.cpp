@@ -47,6 +47,7 @@
 
 #include <sys/mman.h>
 
+#include "host_threads.h"
 #include "internal.h"
 
 namespace arrow {
@@ -164,51 +165,6 @@ int bits_for(uint64_t maxval) {
     int b = 0;
     while (b < 64 && (maxval >> b) != 0) ++b;
     return b;
-}
-
-// Runs fn(lo, hi, t) for t = 0 .. nt-1 over [0, count) split into contiguous
-// ranges of equal size (thread t takes the t-th range), on nt threads; small
-// counts run the same ranges one after the other on the calling thread.
-// Every t is called (possibly with an empty range), so per-thread results
-// are always written.
-template <class F>
-void par_for(int nt, int64_t count, F &&fn) {
-    if (nt <= 1 || count < 4096) {
-        for (int t = 0; t < std::max(nt, 1); ++t)
-            fn(count * t / std::max(nt, 1), count * (t + 1) / std::max(nt, 1), t);
-        return;
-    }
-    std::vector<std::thread> ts;
-    ts.reserve(nt);
-    for (int t = 0; t < nt; ++t) {
-        const int64_t lo = count * t / nt, hi = count * (t + 1) / nt;
-        ts.emplace_back([&fn, lo, hi, t] { fn(lo, hi, t); });
-    }
-    for (auto &th : ts) th.join();
-}
-
-// Runs fn(t) for t = 0 .. nt-1, one thread each (tasks of uneven size).
-template <class F>
-void par_each(int nt, F &&fn) {
-    if (nt <= 1) {
-        fn(0);
-        return;
-    }
-    std::vector<std::thread> ts;
-    ts.reserve(nt);
-    for (int t = 0; t < nt; ++t) ts.emplace_back([&fn, t] { fn(t); });
-    for (auto &th : ts) th.join();
-}
-
-// Exclusive prefix sum of per-thread counts; returns the total.
-int64_t exclusive_scan(Vec<int64_t> &c) {
-    int64_t s = 0;
-    for (auto &v : c) {
-        const int64_t x = v;
-        v = s;
-        s += x;
-    }
-    return s;
 }
 
 inline void atomic_min_u64(uint64_t *p, uint64_t v) {
@@ -1047,9 +1003,7 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
         set_error("nnz must be < 2^31");
         return ARROW_ERR_INVALID_ARG;
     }
-    const int nt = opts.threads > 0
-                       ? opts.threads
-                       : (int)std::max(1u, std::min(256u, std::thread::hardware_concurrency()));
+    const int nt = host_threads(opts.threads);
     {
         // the first bad row (the same message for every thread count)
         Vec<int64_t> bad_col(nt, INT64_MAX), bad_ord(nt, INT64_MAX);

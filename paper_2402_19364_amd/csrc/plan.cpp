@@ -15,10 +15,14 @@
 //    accumulation of Alg. 2, in a fixed order).
 #include "plan.h"
 
+#include <atomic>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
+
+#include "host_threads.h"
 
 namespace arrow {
 namespace {
@@ -130,16 +134,8 @@ static int64_t final_parts(const Plan &p, int dtype) {
     return nwg_of(p.n, p.l0_rpb, l0_blocks_per_wg(dtype));
 }
 
-arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out) {
-    out = nullptr;
-    Plan *pp = new (std::nothrow) Plan();
-    if (!pp) {
-        set_error("host allocation of the plan failed");
-        return ARROW_ERR_OUT_OF_MEMORY;
-    }
-    Plan &p = *pp;
-    p.device = device;
-    p.allocator = g_allocator;
+void plan_build(const Decomp &d, Plan &p, PlanArrays &h) {
+    const int nt = host_threads(0);
     p.n = d.n;
     p.nnz = d.nnz;
     p.b = d.b;
@@ -153,11 +149,15 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
 
     // |A| row sums for the FP8/FP16 scale bound
     {
+        // (a level's rows belong to distinct vertices: its rows run in
+        // parallel, each vertex's sum in the same order as one thread)
         std::vector<double> rs(n, 0.0);
         for (const Level &L : d.levels)
-            for (int64_t q = 0; q < L.n_i; ++q)
-                for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e)
-                    rs[L.vop[q]] += std::fabs((double)L.val[e]);
+            par_for(nt, L.n_i, [&](int64_t lo, int64_t hi, int) {
+                for (int64_t q = lo; q < hi; ++q)
+                    for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e)
+                        rs[L.vop[q]] += std::fabs((double)L.val[e]);
+            });
         for (double v : rs) p.a_inf = std::max(p.a_inf, v);
     }
 
@@ -291,24 +291,34 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     };
     std::vector<int64_t> win_lo(kChunkWindows + 1, n);  // window w: [win_lo[w], win_lo[w+1])
     {
+        // far entries per level-0 column over the rows that split (counted
+        // in parallel over the long rows)
         std::vector<int64_t> cnt(n + 1, 0);
-        int64_t tot = 0;
-        auto count_far = [&](const Level &L, int64_t q, bool map, int64_t r0) {
-            const int64_t nf = far_count(L, q, map, r0);
-            if (nf < kWindowRow) return;
-            for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e) {
-                const int64_t c = map ? pos0[L.vop[L.col[e]]] : L.col[e];
-                if (is_far(c, r0)) ++cnt[c + 1];
-            }
-            tot += nf;
-        };
+        struct LongRow { const Level *L; int64_t q, r0; bool map; };
+        std::vector<LongRow> long_rows;
         for (int64_t r = 0; r < n; ++r)
-            if (chunked0[r]) count_far(L0, r, false, r);
+            if (chunked0[r]) long_rows.push_back({&L0, r, r, false});
         for (int64_t si = 0; si < (int64_t)vrows.size(); ++si)
             if (!fused[si] && up_len(vrows[si]) > kLongRow) {
                 const Level &L = d.levels[vrows[si].level];
-                count_far(L, vrows[si].pos, true, pos0[L.vop[vrows[si].pos]]);
+                long_rows.push_back({&L, vrows[si].pos, (int64_t)pos0[L.vop[vrows[si].pos]], true});
             }
+        std::vector<int64_t> tot_t(nt, 0);
+        par_for(nt, (int64_t)long_rows.size(), [&](int64_t lo, int64_t hi, int t) {
+            for (int64_t j = lo; j < hi; ++j) {
+                const LongRow &lr = long_rows[j];
+                const Level &L = *lr.L;
+                const int64_t nf = far_count(L, lr.q, lr.map, lr.r0);
+                if (nf < kWindowRow) continue;
+                for (int64_t e = L.row_ptr[lr.q]; e < L.row_ptr[lr.q + 1]; ++e) {
+                    const int64_t c = lr.map ? pos0[L.vop[L.col[e]]] : L.col[e];
+                    if (is_far(c, lr.r0)) __atomic_fetch_add(&cnt[c + 1], (int64_t)1, __ATOMIC_RELAXED);
+                }
+                tot_t[t] += nf;
+            }
+        });
+        int64_t tot = 0;
+        for (int64_t x : tot_t) tot += x;
         for (int64_t c = 0; c < n; ++c) cnt[c + 1] += cnt[c];
         win_lo[0] = 0;
         int64_t c = 0;
@@ -322,112 +332,192 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         return (int)(std::upper_bound(win_lo.begin() + 1, win_lo.end() - 1, c) -
                      (win_lo.begin() + 1));
     };
-    std::vector<int32_t> ch_ptr(1, 0), ch_col;
-    std::vector<float> ch_val;
+    auto &ch_ptr = h.ch_ptr, &ch_col = h.ch_col;
+    auto &ch_val = h.ch_val;
+    ch_ptr.assign(1, 0);
     std::vector<int16_t> ch_group;  // window of a chunk, kChunkWindows = not windowed
     std::vector<int32_t> l0_chunk_first(n, -1), l0_chunk_count(n, 0);
-    std::vector<std::pair<int64_t, int64_t>> ents;  // (group * n + column, entry)
-    auto add_chunks = [&](const Level &L, int64_t q, bool map,
-                          int64_t r0) -> std::pair<int32_t, int32_t> {
-        const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
-        const int32_t first = (int32_t)(ch_ptr.size() - 1);
-        const bool split = far_count(L, q, map, r0) >= kWindowRow;
-        ents.clear();
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t c = map ? pos0[L.vop[L.col[e]]] : L.col[e];
-            const int64_t g = split && is_far(c, r0) ? window_of(c) : kChunkWindows;
-            ents.push_back({g * n + c, e});
-        }
-        std::stable_sort(ents.begin(), ents.end(),
-                         [](const std::pair<int64_t, int64_t> &x,
-                            const std::pair<int64_t, int64_t> &y) { return x.first < y.first; });
-        for (size_t i = 0; i < ents.size();) {
-            const int64_t g = ents[i].first / n;
-            size_t j = i;
-            while (j < ents.size() && j - i < (size_t)kChunk && ents[j].first / n == g) ++j;
-            for (size_t u = i; u < j; ++u) {
-                ch_col.push_back((int32_t)(ents[u].first % n));
-                ch_val.push_back(L.val[ents[u].second]);
-            }
-            ch_ptr.push_back((int32_t)ch_col.size());
-            ch_group.push_back((int16_t)g);
-            i = j;
-        }
-        return {first, (int32_t)(ch_ptr.size() - 1) - first};
-    };
-    std::vector<int32_t> l0_ptr(n + 1, 0);
-    std::vector<uint16_t> l0_code;
-    std::vector<int32_t> l0_col;
-    std::vector<float> l0_val;
-    std::vector<int32_t> far_ptr(nblocks_of(n, rpb0) + 1, 0), far_col;
-    std::vector<uint8_t> seen_l0(n, 0), seen_up(n, 0), seen_ch(n, 0);
-    for (int64_t r = 0; r < n; ++r) {
-        const int64_t blk = r / rpb0;
-        if (r % rpb0 == 0) far_ptr[blk] = (int32_t)far_col.size();
-        const int64_t e0 = L0.row_ptr[r], e1 = L0.row_ptr[r + 1];
-        if (chunked0[r]) {
-            auto fc = add_chunks(L0, r, false, r);
-            l0_chunk_first[r] = fc.first;
-            l0_chunk_count[r] = fc.second;
-            ++p.chunked_rows;
-        } else {
-            for (int64_t e = e0; e < e1; ++e) {
-                const int64_t q = L0.col[e];
-                if (p.code16 && q > r + b) {  // a head row's column beyond the band
-                    const int64_t j = (int64_t)far_col.size() - far_ptr[blk];
-                    l0_code.push_back((uint16_t)(3 * (int64_t)b + 1 + j));
-                    far_col.push_back((int32_t)q);
-                } else if (p.code16) {
-                    const int64_t code = q >= r - b ? q - r + b : 2 * b + 1 + q;
-                    l0_code.push_back((uint16_t)code);
-                } else {
-                    l0_col.push_back((int32_t)q);
-                }
-                l0_val.push_back(L0.val[e]);
-                seen_l0[q] = 1;
-            }
-            for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si) {
-                if (!fused[si]) continue;
-                const Level &L = d.levels[vrows[si].level];
-                const int64_t q = vrows[si].pos;
-                for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e) {
-                    const int32_t c = pos0[L.vop[L.col[e]]];
-                    if (p.code16) {
-                        const int64_t j = (int64_t)far_col.size() - far_ptr[blk];
-                        l0_code.push_back((uint16_t)(3 * (int64_t)b + 1 + j));
-                        far_col.push_back(c);
-                    } else {
-                        l0_col.push_back(c);
-                    }
-                    l0_val.push_back(L.val[e]);
-                    seen_l0[c] = 1;
-                }
-            }
-        }
-        l0_ptr[r + 1] = (int32_t)l0_val.size();
-    }
-    far_ptr[nblocks_of(n, rpb0)] = (int32_t)far_col.size();
-    p.l0_nfar = (int64_t)far_col.size();
-    std::vector<int32_t> up_ptr(p.n_up + 1, 0), up_col, up_cptr(p.n_up + 1, 0), up_cidx;
-    std::vector<float> up_val;
     std::vector<std::pair<int32_t, int32_t>> up_chunks(p.n_up, {-1, 0});
+    // The chunked rows (level-0 rows by position, then upper rows in order),
+    // each cut into chunks on its own (threads take rows in turn), then
+    // appended in that order.
+    struct ChunkRow {
+        const Level *L;
+        int64_t q, r0;
+        bool map;
+        int64_t up_row;  // upper row, or -1 for a level-0 row
+        std::vector<int32_t> col, len;  // columns in chunk order, chunk lengths
+        std::vector<float> val;
+        std::vector<int16_t> group;
+    };
+    std::vector<ChunkRow> crows;
+    for (int64_t r = 0; r < n; ++r)
+        if (chunked0[r]) crows.push_back({&L0, r, r, false, -1, {}, {}, {}, {}});
     for (int64_t s = 0; s < p.n_up; ++s) {
         const Level &L = d.levels[up[s].level];
         const int64_t q = up[s].pos;
-        const int64_t e0 = L.row_ptr[q], e1 = L.row_ptr[q + 1];
-        if (e1 - e0 > kLongRow) {
-            up_chunks[s] = add_chunks(L, q, true, pos0[L.vop[q]]);
+        if (L.row_ptr[q + 1] - L.row_ptr[q] > kLongRow)
+            crows.push_back({&L, q, (int64_t)pos0[L.vop[q]], true, s, {}, {}, {}, {}});
+    }
+    {
+        // a row's entries by (group, column), cut into chunks of at most
+        // kChunk entries within a group, ascending column
+        std::atomic<size_t> next{0};
+        par_each(nt, [&](int) {
+            std::vector<std::pair<int64_t, int64_t>> ents;  // (group * n + column, entry)
+            for (size_t j; (j = next.fetch_add(1)) < crows.size();) {
+                ChunkRow &cr = crows[j];
+                const Level &L = *cr.L;
+                const int64_t e0 = L.row_ptr[cr.q], e1 = L.row_ptr[cr.q + 1];
+                const bool split = far_count(L, cr.q, cr.map, cr.r0) >= kWindowRow;
+                ents.clear();
+                for (int64_t e = e0; e < e1; ++e) {
+                    const int64_t c = cr.map ? pos0[L.vop[L.col[e]]] : L.col[e];
+                    const int64_t g = split && is_far(c, cr.r0) ? window_of(c) : kChunkWindows;
+                    ents.push_back({g * n + c, e});
+                }
+                std::stable_sort(ents.begin(), ents.end(),
+                                 [](const std::pair<int64_t, int64_t> &x,
+                                    const std::pair<int64_t, int64_t> &y) { return x.first < y.first; });
+                for (size_t i = 0; i < ents.size();) {
+                    const int64_t g = ents[i].first / n;
+                    size_t k = i;
+                    while (k < ents.size() && k - i < (size_t)kChunk && ents[k].first / n == g) ++k;
+                    for (size_t u = i; u < k; ++u) {
+                        cr.col.push_back((int32_t)(ents[u].first % n));
+                        cr.val.push_back(L.val[ents[u].second]);
+                    }
+                    cr.len.push_back((int32_t)(k - i));
+                    cr.group.push_back((int16_t)g);
+                    i = k;
+                }
+            }
+        });
+        for (size_t j = 0; j < crows.size(); ++j) {
+            ChunkRow &cr = crows[j];
+            const int32_t first = (int32_t)(ch_ptr.size() - 1);
+            ch_col.insert(ch_col.end(), cr.col.begin(), cr.col.end());
+            ch_val.insert(ch_val.end(), cr.val.begin(), cr.val.end());
+            for (size_t c = 0; c < cr.len.size(); ++c) {
+                ch_ptr.push_back(ch_ptr.back() + cr.len[c]);
+                ch_group.push_back(cr.group[c]);
+            }
+            const int32_t count = (int32_t)cr.len.size();
+            if (cr.up_row < 0) {
+                l0_chunk_first[cr.q] = first;
+                l0_chunk_count[cr.q] = count;
+            } else {
+                up_chunks[cr.up_row] = {first, count};
+            }
             ++p.chunked_rows;
-        } else {
-            for (int64_t e = e0; e < e1; ++e) {
-                const int32_t c = pos0[L.vop[L.col[e]]];
-                up_col.push_back(c);
-                up_val.push_back(L.val[e]);
-                seen_up[c] = 1;
+            std::vector<int32_t>().swap(cr.col);
+            std::vector<float>().swap(cr.val);
+        }
+    }
+    auto &l0_ptr = h.l0_ptr;
+    auto &l0_code = h.l0_code;
+    auto &l0_col = h.l0_col;
+    auto &l0_val = h.l0_val;
+    auto &far_ptr = h.far_ptr, &far_col = h.far_col;
+    std::vector<uint8_t> seen_l0(n, 0), seen_up(n, 0), seen_ch(n, 0);
+    auto mark = [](std::vector<uint8_t> &seen, int64_t c) {
+        __atomic_store_n(&seen[c], (uint8_t)1, __ATOMIC_RELAXED);
+    };
+    // level-0 rows: entry counts per row and far-table counts per block,
+    // then every block's codes (or columns), values and far table in parallel
+    const int64_t nblk0 = nblocks_of(n, rpb0);
+    l0_ptr.assign(n + 1, 0);
+    far_ptr.assign(nblk0 + 1, 0);
+    par_for(nt, nblk0, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t blk = lo; blk < hi; ++blk) {
+            int64_t nf = 0;
+            for (int64_t r = blk * rpb0; r < std::min<int64_t>(n, (blk + 1) * rpb0); ++r) {
+                if (chunked0[r]) continue;
+                int64_t len = L0.row_ptr[r + 1] - L0.row_ptr[r];
+                if (p.code16) nf += head_far(r);
+                for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si)
+                    if (fused[si]) {
+                        len += up_len(vrows[si]);
+                        if (p.code16) nf += up_len(vrows[si]);
+                    }
+                l0_ptr[r + 1] = (int32_t)len;
+            }
+            far_ptr[blk + 1] = (int32_t)nf;
+        }
+    });
+    for (int64_t r = 0; r < n; ++r) l0_ptr[r + 1] += l0_ptr[r];
+    for (int64_t blk = 0; blk < nblk0; ++blk) far_ptr[blk + 1] += far_ptr[blk];
+    if (p.code16)
+        l0_code.resize(l0_ptr[n]);
+    else
+        l0_col.resize(l0_ptr[n]);
+    l0_val.resize(l0_ptr[n]);
+    far_col.resize(far_ptr[nblk0]);
+    par_for(nt, nblk0, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t blk = lo; blk < hi; ++blk) {
+            int64_t f = far_ptr[blk];
+            for (int64_t r = blk * rpb0; r < std::min<int64_t>(n, (blk + 1) * rpb0); ++r) {
+                if (chunked0[r]) continue;
+                int64_t o = l0_ptr[r];
+                for (int64_t e = L0.row_ptr[r]; e < L0.row_ptr[r + 1]; ++e, ++o) {
+                    const int64_t q = L0.col[e];
+                    if (p.code16 && q > r + b) {  // a head row's column beyond the band
+                        l0_code[o] = (uint16_t)(3 * (int64_t)b + 1 + (f - far_ptr[blk]));
+                        far_col[f++] = (int32_t)q;
+                    } else if (p.code16) {
+                        const int64_t code = q >= r - b ? q - r + b : 2 * b + 1 + q;
+                        l0_code[o] = (uint16_t)code;
+                    } else {
+                        l0_col[o] = (int32_t)q;
+                    }
+                    l0_val[o] = L0.val[e];
+                    mark(seen_l0, q);
+                }
+                for (int64_t si = vrow_ptr[r]; si < vrow_ptr[r + 1]; ++si) {
+                    if (!fused[si]) continue;
+                    const Level &L = d.levels[vrows[si].level];
+                    const int64_t q = vrows[si].pos;
+                    for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e, ++o) {
+                        const int32_t c = pos0[L.vop[L.col[e]]];
+                        if (p.code16) {
+                            l0_code[o] = (uint16_t)(3 * (int64_t)b + 1 + (f - far_ptr[blk]));
+                            far_col[f++] = c;
+                        } else {
+                            l0_col[o] = c;
+                        }
+                        l0_val[o] = L.val[e];
+                        mark(seen_l0, c);
+                    }
+                }
             }
         }
-        up_ptr[s + 1] = (int32_t)up_val.size();
+    });
+    p.l0_nfar = (int64_t)far_col.size();
+    // upper rows that are not chunked: columns mapped to level-0 positions
+    auto &up_ptr = h.up_ptr, &up_col = h.up_col, &up_cptr = h.up_cptr, &up_cidx = h.up_cidx;
+    auto &up_val = h.up_val;
+    up_ptr.assign(p.n_up + 1, 0);
+    up_cptr.assign(p.n_up + 1, 0);
+    for (int64_t s = 0; s < p.n_up; ++s) {
+        const int64_t len = up_len(up[s]);
+        up_ptr[s + 1] = up_ptr[s] + (int32_t)(len > kLongRow ? 0 : len);
     }
+    up_col.resize(up_ptr[p.n_up]);
+    up_val.resize(up_ptr[p.n_up]);
+    par_for(nt, p.n_up, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t s = lo; s < hi; ++s) {
+            if (up_ptr[s + 1] == up_ptr[s]) continue;
+            const Level &L = d.levels[up[s].level];
+            const int64_t q = up[s].pos;
+            int64_t o = up_ptr[s];
+            for (int64_t e = L.row_ptr[q]; e < L.row_ptr[q + 1]; ++e, ++o) {
+                const int32_t c = pos0[L.vop[L.col[e]]];
+                up_col[o] = c;
+                up_val[o] = L.val[e];
+                mark(seen_up, c);
+            }
+        }
+    });
     p.n_chunks = (int64_t)ch_ptr.size() - 1;
     // Chunk placement.  Workgroup w of the chunk pass runs on XCD w % kXcds
     // (dispatch is round-robin over the XCDs) and takes kChunksPerBlock
@@ -442,10 +532,20 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     {
         std::vector<std::vector<int32_t>> grp(kChunkWindows + 1);
         for (int64_t c = 0; c < p.n_chunks; ++c) grp[ch_group[c]].push_back((int32_t)c);
-        for (auto &g : grp)
-            std::stable_sort(g.begin(), g.end(), [&](int32_t x, int32_t y) {
-                return ch_col[ch_ptr[x]] < ch_col[ch_ptr[y]];
-            });
+        // (groups sorted in parallel, on (first column, chunk) keys)
+        std::atomic<int> next_g{0};
+        par_each(std::min(nt, kChunkWindows + 1), [&](int) {
+            std::vector<std::pair<int32_t, int32_t>> key;
+            for (int w; (w = next_g.fetch_add(1)) <= kChunkWindows;) {
+                std::vector<int32_t> &g = grp[w];
+                key.resize(g.size());
+                for (size_t i = 0; i < g.size(); ++i) key[i] = {ch_col[ch_ptr[g[i]]], g[i]};
+                std::stable_sort(key.begin(), key.end(),
+                                 [](const std::pair<int32_t, int32_t> &x,
+                                    const std::pair<int32_t, int32_t> &y) { return x.first < y.first; });
+                for (size_t i = 0; i < g.size(); ++i) g[i] = key[i].second;
+            }
+        });
         constexpr int U = kChunksPerBlock;
         std::vector<std::vector<std::pair<size_t, int>>> xcd_units(kXcds);  // (group, first)
         for (int w = 0; w <= kChunkWindows; ++w)
@@ -464,19 +564,23 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
                 for (size_t i = i0; i < std::min(g.size(), i0 + U); ++i)
                     slot_chunk[(j * kXcds + x) * U + (i - i0)] = g[i];
             }
-        std::vector<int32_t> nptr(p.ch_slots + 1, 0), ncol;
-        std::vector<float> nval;
-        ncol.reserve(ch_col.size());
-        nval.reserve(ch_val.size());
+        std::vector<int32_t> nptr(p.ch_slots + 1, 0), ncol(ch_col.size());
+        std::vector<float> nval(ch_val.size());
         for (int64_t slot = 0; slot < p.ch_slots; ++slot) {
             const int32_t c = slot_chunk[slot];
-            if (c >= 0) {
-                chunk_slot[c] = (int32_t)slot;
-                ncol.insert(ncol.end(), ch_col.begin() + ch_ptr[c], ch_col.begin() + ch_ptr[c + 1]);
-                nval.insert(nval.end(), ch_val.begin() + ch_ptr[c], ch_val.begin() + ch_ptr[c + 1]);
-            }
-            nptr[slot + 1] = (int32_t)ncol.size();
+            nptr[slot + 1] = nptr[slot] + (c >= 0 ? ch_ptr[c + 1] - ch_ptr[c] : 0);
+            if (c >= 0) chunk_slot[c] = (int32_t)slot;
         }
+        par_for(nt, p.ch_slots, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t slot = lo; slot < hi; ++slot) {
+                const int32_t c = slot_chunk[slot];
+                if (c < 0) continue;
+                std::copy(ch_col.begin() + ch_ptr[c], ch_col.begin() + ch_ptr[c + 1],
+                          ncol.begin() + nptr[slot]);
+                std::copy(ch_val.begin() + ch_ptr[c], ch_val.begin() + ch_ptr[c + 1],
+                          nval.begin() + nptr[slot]);
+            }
+        });
         ch_ptr.swap(nptr);
         ch_col.swap(ncol);
         ch_val.swap(nval);
@@ -491,7 +595,8 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     }
     // partial rows listed by the level-0 rows: own chunks, then the upper rows
     // of the same vertex by level
-    std::vector<int32_t> l0_cptr(n + 1, 0), l0_cidx;
+    auto &l0_cptr = h.l0_cptr, &l0_cidx = h.l0_cidx;
+    l0_cptr.assign(n + 1, 0);
     for (int64_t r = 0; r < n; ++r) {
         for (int32_t c = 0; c < l0_chunk_count[r]; ++c)
             l0_cidx.push_back((int32_t)(p.n_up + chunk_slot[l0_chunk_first[r] + c]));
@@ -530,14 +635,14 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
         o.push_back(ptr[rows]);
         return o;
     };
-    std::vector<int32_t> l0_blk_e = block_offsets(n, rpb0, l0_ptr);
-    std::vector<int32_t> l0_blk_c = block_offsets(n, rpb0, l0_cptr);
-    std::vector<int32_t> up_blk_e, up_blk_c;
+    h.l0_blk_e = block_offsets(n, rpb0, l0_ptr);
+    h.l0_blk_c = block_offsets(n, rpb0, l0_cptr);
+    auto &up_blk_e = h.up_blk_e, &up_blk_c = h.up_blk_c;
     if (p.n_up > 0) {
         up_blk_e = block_offsets(p.n_up, kRowsPerBlock, up_ptr);
         up_blk_c = block_offsets(p.n_up, kRowsPerBlock, up_cptr);
     }
-    std::vector<uint8_t> l0_order, up_order;
+    auto &l0_order = h.l0_order, &up_order = h.up_order;
     if (p.l0_batch_auto == kBatchWide) l0_order = block_order(n, rpb0, l0_ptr, l0_cptr);
     if (p.up_batch_auto == kBatchWide && p.n_up > 0)
         up_order = block_order(p.n_up, kRowsPerBlock, up_ptr, up_cptr);
@@ -549,6 +654,21 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     p.distinct_l0 = count_true(seen_l0);
     p.distinct_up = count_true(seen_up);
     p.distinct_ch = count_true(seen_ch);
+}
+
+arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out) {
+    out = nullptr;
+    Plan *pp = new (std::nothrow) Plan();
+    if (!pp) {
+        set_error("host allocation of the plan failed");
+        return ARROW_ERR_OUT_OF_MEMORY;
+    }
+    Plan &p = *pp;
+    p.device = device;
+    p.allocator = g_allocator;
+    PlanArrays h;
+    plan_build(d, p, h);
+    const Level &L0 = d.levels[0];
 
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) {
@@ -559,37 +679,37 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     arrow_status_t st = ARROW_OK;
 #define UP(dst, src)                                \
     if (st == ARROW_OK) st = upload(p, dst, src, stream);
-    UP(p.l0_ptr, l0_ptr);
+    UP(p.l0_ptr, h.l0_ptr);
     if (p.code16) {
         uint16_t *codes = nullptr;
-        UP(codes, l0_code);
+        UP(codes, h.l0_code);
         p.l0_idx = codes;
     } else {
         int32_t *cols = nullptr;
-        UP(cols, l0_col);
+        UP(cols, h.l0_col);
         p.l0_idx = cols;
     }
-    UP(p.l0_val, l0_val);
-    UP(p.l0_cptr, l0_cptr);
-    UP(p.l0_cidx, l0_cidx);
-    UP(p.l0_order, l0_order);
-    UP(p.up_order, up_order);
-    UP(p.l0_blk_e, l0_blk_e);
-    UP(p.l0_blk_c, l0_blk_c);
-    UP(p.up_blk_e, up_blk_e);
-    UP(p.up_blk_c, up_blk_c);
+    UP(p.l0_val, h.l0_val);
+    UP(p.l0_cptr, h.l0_cptr);
+    UP(p.l0_cidx, h.l0_cidx);
+    UP(p.l0_order, h.l0_order);
+    UP(p.up_order, h.up_order);
+    UP(p.l0_blk_e, h.l0_blk_e);
+    UP(p.l0_blk_c, h.l0_blk_c);
+    UP(p.up_blk_e, h.up_blk_e);
+    UP(p.up_blk_c, h.up_blk_c);
     if (p.l0_nfar > 0) {
-        UP(p.l0_fptr, far_ptr);
-        UP(p.l0_fcol, far_col);
+        UP(p.l0_fptr, h.far_ptr);
+        UP(p.l0_fcol, h.far_col);
     }
-    UP(p.up_ptr, up_ptr);
-    UP(p.up_col, up_col);
-    UP(p.up_val, up_val);
-    UP(p.up_cptr, up_cptr);
-    UP(p.up_cidx, up_cidx);
-    UP(p.ch_ptr, ch_ptr);
-    UP(p.ch_col, ch_col);
-    UP(p.ch_val, ch_val);
+    UP(p.up_ptr, h.up_ptr);
+    UP(p.up_col, h.up_col);
+    UP(p.up_val, h.up_val);
+    UP(p.up_cptr, h.up_cptr);
+    UP(p.up_cidx, h.up_cidx);
+    UP(p.ch_ptr, h.ch_ptr);
+    UP(p.ch_col, h.ch_col);
+    UP(p.ch_val, h.ch_val);
     UP(p.vop0, L0.vop);
 #undef UP
     if (st == ARROW_OK) {

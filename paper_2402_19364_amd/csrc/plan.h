@@ -102,6 +102,20 @@ struct Plan {
     std::vector<hipEvent_t> ev_pool;
 };
 
+// Host arrays of a plan, before upload (the device arrays of the same names).
+struct PlanArrays {
+    std::vector<int32_t> l0_ptr, l0_col, l0_cptr, l0_cidx, l0_blk_e, l0_blk_c, far_ptr, far_col;
+    std::vector<uint16_t> l0_code;
+    std::vector<float> l0_val;
+    std::vector<uint8_t> l0_order, up_order;
+    std::vector<int32_t> up_ptr, up_col, up_cptr, up_cidx, up_blk_e, up_blk_c;
+    std::vector<float> up_val;
+    std::vector<int32_t> ch_ptr, ch_col;
+    std::vector<float> ch_val;
+};
+// Builds the plan's host arrays and fills the scalar fields of `p` (no
+// device work).
+void plan_build(const Decomp &d, Plan &p, PlanArrays &h);
 arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan *&out);
 void plan_destroy(Plan *p);
 
