@@ -755,7 +755,7 @@ void boruvka_rounds(int nt, Vec<int32_t> &parent, Vec<int32_t> &cu,
         par_for(nt, nr, [&](int64_t lo, int64_t hi, int) {
             for (int64_t j = lo; j < hi; ++j) best[roots[j]] = UINT64_MAX;
         });
-        // only labels linked this round move
+        // only the labels linked in this Boruvka round move
         jump_to_roots(nt, parent, roots);
     }
     for (auto &q : ids) chosen.insert(chosen.end(), q.begin(), q.end());
@@ -840,7 +840,7 @@ void forest_from_rows(int nt, int64_t n, const Vec<int64_t> &ptr,
         return a < b ? sm_output(ls, (uint64_t)a * un + (uint64_t)b)
                      : sm_output(ls, (uint64_t)b * un + (uint64_t)a);
     };
-    // round 1: every vertex of G - H with an edge picks its lightest one
+    // first Boruvka round: every vertex of G - H with an edge picks its lightest one
     Vec<int32_t> pick(n, -1), parent(n);
     par_for(nt, n, [&](int64_t lo, int64_t hi, int) {
         for (int64_t v = lo; v < hi; ++v) {
@@ -904,7 +904,7 @@ void forest_from_rows(int nt, int64_t n, const Vec<int64_t> &ptr,
         });
     }
     Vec<int32_t>().swap(pick);
-    // the edges above the diagonal that join two components after round 1,
+    // the edges above the diagonal that join two components after the first round,
     // by rows (columns are sorted within a row: the entries above the
     // diagonal are a row's tail); thread t writes them from the offset of
     // its rows' entries above the diagonal
