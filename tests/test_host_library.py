@@ -83,6 +83,27 @@ def test_nonsymmetric_medium_decomposition_matches_oracle_on_any_thread_count():
         _assert_same(A_.Decomposition.from_matrix(B, 32, seed=6, threads=t).levels(), ref)
 
 
+def test_concurrent_decompositions_match_sequential_ones():
+    # two host threads decompose at once (ctypes releases the GIL), sharing
+    # the library's cache of large working blocks
+    import threading
+    mats = [W.make_matrix("rmat", 14, "row_normalized", 41, 42, 16),
+            W.make_matrix("grid3d", 24, "sym_laplacian", 0, 1)]
+    ref = [A_.Decomposition.from_matrix(M, 64, seed=9, threads=2).levels() for M in mats]
+    got = [None, None]
+
+    def work(i):
+        got[i] = A_.Decomposition.from_matrix(mats[i], 64, seed=9, threads=2).levels()
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for i in range(2):
+        _assert_same(got[i], ref[i])
+
+
 @pytest.mark.parametrize("cfg", ["grid64"])
 def test_config_small_decomposition(cfg):
     w = W.WORKLOADS[cfg]
