@@ -295,6 +295,30 @@ void layout_forest(int nt, int64_t n, const Vec<int32_t> &fu, const Vec<int32_t>
     });
 }
 
+// Sorts distinct vertex ids in [0, n) increasingly: least-significant-digit
+// radix sort with 11-bit digits for long lists, std::sort for short ones.
+void sort_ids(Vec<int32_t> &v, int64_t n, Vec<int32_t> &tmp) {
+    if (v.size() < 1024) {
+        std::sort(v.begin(), v.end());
+        return;
+    }
+    constexpr int kBits = 11, kR = 1 << kBits;
+    tmp.resize(v.size());
+    int64_t cnt[kR];
+    for (int shift = 0; shift == 0 || (n - 1) >> shift; shift += kBits) {
+        std::fill(cnt, cnt + kR, 0);
+        for (int32_t x : v) ++cnt[(x >> shift) & (kR - 1)];
+        int64_t s = 0;
+        for (int d = 0; d < kR; ++d) {
+            const int64_t c = cnt[d];
+            cnt[d] = s;
+            s += c;
+        }
+        for (int32_t x : v) tmp[cnt[(x >> shift) & (kR - 1)]++] = x;
+        v.swap(tmp);
+    }
+}
+
 // Separator arrangement (Section 5.2) of the graph with edges (fu, fv):
 // a vertex set is laid out as its connected components in increasing size
 // (ties: smaller smallest id), each recursively; a connected set places a
@@ -364,6 +388,7 @@ void layout_separator(int64_t n, const Vec<int32_t> &fu, const Vec<int32_t> &fv,
         Vec<int32_t> vs;
     };
     Vec<Item> stack;
+    Vec<int32_t> sort_tmp;
     stack.push_back({false, std::move(top)});
     Vec<Vec<int32_t>> comps;
     while (!stack.empty()) {
@@ -377,7 +402,7 @@ void layout_separator(int64_t n, const Vec<int32_t> &fu, const Vec<int32_t> &fv,
             continue;
         }
         // connected components of the set, seeds in increasing id
-        std::sort(it.vs.begin(), it.vs.end());
+        sort_ids(it.vs, n, sort_tmp);
         ++cur;
         comps.clear();
         for (int32_t v0 : it.vs) {
