@@ -38,6 +38,7 @@
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -327,12 +328,18 @@ void sort_ids(Vec<int32_t> &v, int64_t n, Vec<int32_t> &tmp) {
 // reached by a BFS from the set's smallest id) at which the BFS has reached
 // at least half of the set.  BFS visits neighbours in increasing id.  Appends
 // to `order`, marks `placed`.
-void layout_separator(int64_t n, const Vec<int32_t> &fu, const Vec<int32_t> &fv,
+//
+// The components of a set are disjoint and not adjacent through live
+// vertices, so large ones are laid out on threads of their own (at most nt
+// at a time), each into its own list; the lists are joined in component
+// order, so the result does not depend on the thread count.  Visit marks
+// take globally increasing stamps.
+void layout_separator(int nt, int64_t n, const Vec<int32_t> &fu, const Vec<int32_t> &fv,
                       Vec<int32_t> &order, Vec<uint8_t> &placed) {
-    const size_t m = fu.size();
+    const int64_t m = (int64_t)fu.size();
     if (m == 0) return;
     Vec<int64_t> aptr(n + 1, 0);
-    for (size_t e = 0; e < m; ++e) {
+    for (int64_t e = 0; e < m; ++e) {
         ++aptr[fu[e] + 1];
         ++aptr[fv[e] + 1];
     }
@@ -340,114 +347,132 @@ void layout_separator(int64_t n, const Vec<int32_t> &fu, const Vec<int32_t> &fv,
     Vec<int32_t> adj(2 * m);
     {
         Vec<int64_t> fill(aptr.begin(), aptr.end() - 1);
-        for (size_t e = 0; e < m; ++e) {
+        for (int64_t e = 0; e < m; ++e) {
             adj[fill[fu[e]]++] = fv[e];
             adj[fill[fv[e]]++] = fu[e];
         }
     }
     Vec<uint8_t> alive(n, 0);
+    par_for(nt, n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t v = lo; v < hi; ++v)
+            if (aptr[v + 1] > aptr[v]) {
+                std::sort(adj.begin() + aptr[v], adj.begin() + aptr[v + 1]);
+                alive[v] = 1;
+            }
+    });
     Vec<int32_t> top;
     for (int64_t v = 0; v < n; ++v)
-        if (aptr[v + 1] > aptr[v]) {
-            std::sort(adj.begin() + aptr[v], adj.begin() + aptr[v + 1]);
-            alive[v] = 1;
-            top.push_back((int32_t)v);
+        if (alive[v]) top.push_back((int32_t)v);
+    Vec<int32_t> stamp(n, 0);  // visit marks: stamp[v] == the visit's stamp
+    std::atomic<int32_t> next_stamp{0};
+    std::atomic<int> spare{nt - 1};  // threads that may still be started
+    constexpr size_t kParallelSet = size_t(1) << 16;
+    auto take_thread = [&] {
+        int s = spare.load();
+        while (s > 0 && !spare.compare_exchange_weak(s, s - 1)) {
         }
-    Vec<int32_t> stamp(n, 0);  // visit marks: stamp[v] == cur
-    int32_t cur = 0;
-    // BFS inside the alive vertices from `start`; `out` gets the visit order,
-    // `lev` the offsets of the levels in it
-    Vec<int32_t> bfs;
-    Vec<int64_t> lev;
-    auto bfs_levels = [&](int32_t start) {
-        ++cur;
-        bfs.clear();
-        lev.clear();
-        bfs.push_back(start);
-        stamp[start] = cur;
-        lev.push_back(0);
-        size_t h = 0;
-        while (h < bfs.size()) {
-            const size_t end = bfs.size();
-            lev.push_back((int64_t)end);
-            for (; h < end; ++h) {
-                const int32_t v = bfs[h];
-                for (int64_t a = aptr[v]; a < aptr[v + 1]; ++a) {
-                    const int32_t w = adj[a];
-                    if (alive[w] && stamp[w] != cur) {
-                        stamp[w] = cur;
-                        bfs.push_back(w);
+        return s > 0;
+    };
+    // lays out the set vs (a union of components of the live graph) into out
+    std::function<void(Vec<int32_t> &&, Vec<int32_t> &)> solve = [&](Vec<int32_t> &&vs,
+                                                                       Vec<int32_t> &out) {
+        Vec<int32_t> sort_tmp, bfs;
+        Vec<int64_t> lev;
+        // BFS inside the live vertices from `start`: the visit order in bfs,
+        // level i in bfs[lev[i] .. lev[i+1]) (the last entry equals bfs.size())
+        auto bfs_levels = [&](int32_t start) {
+            const int32_t cur = ++next_stamp;
+            bfs.clear();
+            lev.clear();
+            bfs.push_back(start);
+            stamp[start] = cur;
+            lev.push_back(0);
+            size_t h = 0;
+            while (h < bfs.size()) {
+                const size_t end = bfs.size();
+                lev.push_back((int64_t)end);
+                for (; h < end; ++h) {
+                    const int32_t v = bfs[h];
+                    for (int64_t a = aptr[v]; a < aptr[v + 1]; ++a) {
+                        const int32_t w = adj[a];
+                        if (alive[w] && stamp[w] != cur) {
+                            stamp[w] = cur;
+                            bfs.push_back(w);
+                        }
                     }
                 }
             }
-        }
-        // lev[i] .. lev[i+1]: level i (the last entry equals bfs.size())
-    };
-    struct Item {
-        bool place;
-        Vec<int32_t> vs;
-    };
-    Vec<Item> stack;
-    Vec<int32_t> sort_tmp;
-    stack.push_back({false, std::move(top)});
-    Vec<Vec<int32_t>> comps;
-    while (!stack.empty()) {
-        Item it = std::move(stack.back());
-        stack.pop_back();
-        if (it.place) {
-            for (int32_t v : it.vs) {
-                order.push_back(v);
-                placed[v] = 1;
-            }
-            continue;
-        }
-        // connected components of the set, seeds in increasing id
-        sort_ids(it.vs, n, sort_tmp);
-        ++cur;
-        comps.clear();
-        for (int32_t v0 : it.vs) {
-            if (stamp[v0] == cur) continue;
-            stamp[v0] = cur;
-            Vec<int32_t> comp(1, v0);
-            for (size_t h = 0; h < comp.size(); ++h) {
-                const int32_t v = comp[h];
-                for (int64_t a = aptr[v]; a < aptr[v + 1]; ++a) {
-                    const int32_t w = adj[a];
-                    if (alive[w] && stamp[w] != cur) {
-                        stamp[w] = cur;
-                        comp.push_back(w);
+        };
+        for (;;) {
+            // connected components of the set, seeds in increasing id
+            sort_ids(vs, n, sort_tmp);
+            const int32_t cur = ++next_stamp;
+            Vec<Vec<int32_t>> comps;
+            for (int32_t v0 : vs) {
+                if (stamp[v0] == cur) continue;
+                stamp[v0] = cur;
+                Vec<int32_t> comp(1, v0);
+                for (size_t h = 0; h < comp.size(); ++h) {
+                    const int32_t v = comp[h];
+                    for (int64_t a = aptr[v]; a < aptr[v + 1]; ++a) {
+                        const int32_t w = adj[a];
+                        if (alive[w] && stamp[w] != cur) {
+                            stamp[w] = cur;
+                            comp.push_back(w);
+                        }
                     }
                 }
+                comps.push_back(std::move(comp));
             }
-            comps.push_back(std::move(comp));
+            Vec<int32_t>().swap(vs);
+            if (comps.size() > 1) {
+                // comp[0] is each component's smallest id
+                std::stable_sort(comps.begin(), comps.end(),
+                                 [](const Vec<int32_t> &x, const Vec<int32_t> &y) {
+                                     return x.size() != y.size() ? x.size() < y.size()
+                                                                 : x[0] < y[0];
+                                 });
+                Vec<Vec<int32_t>> outs(comps.size());
+                std::vector<std::thread> ts;
+                for (size_t j = 0; j < comps.size(); ++j) {
+                    if (comps[j].size() >= kParallelSet && take_thread()) {
+                        ts.emplace_back([&, j] {
+                            solve(std::move(comps[j]), outs[j]);
+                            spare.fetch_add(1);
+                        });
+                    } else {
+                        solve(std::move(comps[j]), outs[j]);
+                    }
+                }
+                for (auto &th : ts) th.join();
+                for (auto &o : outs) out.insert(out.end(), o.begin(), o.end());
+                return;
+            }
+            Vec<int32_t> comp = std::move(comps[0]);
+            if (comp.size() == 1) {
+                out.push_back(comp[0]);
+                alive[comp[0]] = 0;
+                return;
+            }
+            bfs_levels(comp[0]);
+            bfs_levels(bfs.back());
+            size_t li = 0;
+            while (2 * (size_t)lev[li + 1] < comp.size()) ++li;
+            for (int64_t i = lev[li]; i < lev[li + 1]; ++i) {
+                out.push_back(bfs[i]);
+                alive[bfs[i]] = 0;
+            }
+            // then the rest of the set
+            for (int32_t v : comp)
+                if (alive[v]) vs.push_back(v);
+            if (vs.empty()) return;
         }
-        if (comps.size() > 1) {
-            // comp[0] is each component's smallest id
-            std::stable_sort(comps.begin(), comps.end(),
-                             [](const Vec<int32_t> &a, const Vec<int32_t> &b) {
-                                 return a.size() != b.size() ? a.size() < b.size() : a[0] < b[0];
-                             });
-            for (size_t j = comps.size(); j-- > 0;) stack.push_back({false, std::move(comps[j])});
-            continue;
-        }
-        Vec<int32_t> comp = std::move(comps[0]);
-        if (comp.size() == 1) {
-            order.push_back(comp[0]);
-            placed[comp[0]] = 1;
-            alive[comp[0]] = 0;
-            continue;
-        }
-        bfs_levels(comp[0]);
-        bfs_levels(bfs.back());
-        size_t li = 0;
-        while (2 * (size_t)lev[li + 1] < comp.size()) ++li;
-        Vec<int32_t> sep(bfs.begin() + lev[li], bfs.begin() + lev[li + 1]);
-        for (int32_t v : sep) alive[v] = 0;
-        Vec<int32_t> rest;
-        for (int32_t v : comp)
-            if (alive[v]) rest.push_back(v);
-        if (!rest.empty()) stack.push_back({false, std::move(rest)});
-        stack.push_back({true, std::move(sep)});
+    };
+    Vec<int32_t> out;
+    solve(std::move(top), out);
+    for (int32_t v : out) {
+        order.push_back(v);
+        placed[v] = 1;
     }
 }
 
@@ -1199,7 +1224,7 @@ arrow_status_t decompose(int64_t n, const int64_t *row_ptr, const int32_t *col,
                         gu.push_back(eu[e]);
                         gv.push_back(ev[e]);
                     }
-                layout_separator(n, gu, gv, order, placed);
+                layout_separator(nt, n, gu, gv, order, placed);
             }
         }
         // then the unplaced vertices that hold entries, then the rest, by id
