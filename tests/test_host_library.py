@@ -104,6 +104,17 @@ def test_concurrent_decompositions_match_sequential_ones():
         _assert_same(got[i], ref[i])
 
 
+def test_separator_decomposition_same_on_any_thread_count():
+    # components of 2^16 vertices and more are laid out on threads of their
+    # own: a 400 x 400 grid splits into such components at its first levels
+    A = W.make_matrix("grid2d", 400, "sym_laplacian", 0, 1)
+    ref = A_.Decomposition.from_matrix(A, 400, seed=3, la=A_.LA_SEPARATOR, threads=1).levels()
+    D.validate(A, ref, 400)
+    for t in (3, 8):
+        got = A_.Decomposition.from_matrix(A, 400, seed=3, la=A_.LA_SEPARATOR, threads=t).levels()
+        _assert_same(got, ref)
+
+
 @pytest.mark.parametrize("cfg", ["grid64"])
 def test_config_small_decomposition(cfg):
     w = W.WORKLOADS[cfg]
