@@ -604,20 +604,16 @@ void undirected_edges(int nt, int64_t n, const Vec<int32_t> &R,
         bstart[P] = s2;
     }
     const int64_t m2 = bstart[P];
-    Vec<uint64_t> k1(m1), k2(m2);
+    Vec<uint64_t> k2(m2);
     Vec<int32_t> r2(m2), c2(m2);
     par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
-        int64_t o = c1[t];
         int64_t *bo = &boff[(size_t)t * P];
-        for (int64_t e = lo; e < hi; ++e) {
-            if (R[e] < C[e]) {
-                k1[o++] = (uint64_t)R[e] * un + (uint64_t)C[e];
-            } else if (R[e] > C[e]) {
+        for (int64_t e = lo; e < hi; ++e)
+            if (R[e] > C[e]) {
                 const int64_t d = bo[bucket_of(C[e])]++;
                 r2[d] = R[e];
                 c2[d] = C[e];
             }
-        }
     });
     // within a bucket the entries are in CSR order (increasing r): a stable
     // counting sort by c leaves them sorted by (c, r)
@@ -639,11 +635,13 @@ void undirected_edges(int nt, int64_t n, const Vec<int32_t> &R,
     Vec<int32_t>().swap(c2);
     if (symmetric) {
         // the entries below the diagonal, transposed and sorted, equal the
-        // ones above it exactly when the pattern is symmetric
+        // ones above it (in CSR order) exactly when the pattern is symmetric
         Vec<uint8_t> same(nt, 1);
         if (m1 == m2)
-            par_for(nt, m1, [&](int64_t lo, int64_t hi, int t) {
-                for (int64_t i = lo; i < hi && same[t]; ++i) same[t] = k1[i] == k2[i];
+            par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+                int64_t o = c1[t];
+                for (int64_t e = lo; e < hi && same[t]; ++e)
+                    if (R[e] < C[e]) same[t] = k2[o++] == (uint64_t)R[e] * un + (uint64_t)C[e];
             });
         *symmetric = m1 == m2;
         for (int t = 0; t < nt; ++t) *symmetric = *symmetric && same[t];
@@ -654,6 +652,12 @@ void undirected_edges(int nt, int64_t n, const Vec<int32_t> &R,
             return;
         }
     }
+    Vec<uint64_t> k1(m1);
+    par_for(nt, m, [&](int64_t lo, int64_t hi, int t) {
+        int64_t o = c1[t];
+        for (int64_t e = lo; e < hi; ++e)
+            if (R[e] < C[e]) k1[o++] = (uint64_t)R[e] * un + (uint64_t)C[e];
+    });
     // merge the two sorted lists per range of u, dropping duplicates
     Vec<int64_t> s1(nt + 1), s2(nt + 1), cnt(nt, 0);
     for (int t = 0; t <= nt; ++t) {
