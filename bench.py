@@ -488,7 +488,8 @@ def main():
 
     kb = {kid: plan.kernel_bytes(kid, k, dtype) for kid in arrow.KERNEL_NAMES}
     bytes_iter = sum(kb[kid] for kid in (arrow.KERNEL_CHUNKS, arrow.KERNEL_UPPER,
-                                         arrow.KERNEL_LEVEL0, arrow.KERNEL_NORM))
+                                         arrow.KERNEL_COMBINE, arrow.KERNEL_LEVEL0,
+                                         arrow.KERNEL_NORM))
     # minimum-byte model of one product (what a plain CSR SpMM must move):
     # values and column indices, row offsets, X read once, Y written once
     es = arrow.ELEM_SIZE[arrow.DTYPES[dtype]]

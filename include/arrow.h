@@ -242,7 +242,8 @@ enum {
     ARROW_KERNEL_LEVEL0 = 2,  /* level-0 band + head columns + cross-level sum + store */
     ARROW_KERNEL_NORM = 3,    /* FP64 column norms and next scales */
     ARROW_KERNEL_PERMUTE = 4, /* permute in / out */
-    ARROW_KERNEL_COUNT = 5
+    ARROW_KERNEL_COMBINE = 5, /* sums of long partial-row lists (hub rows), before level 0 */
+    ARROW_KERNEL_COUNT = 6
 };
 
 /*

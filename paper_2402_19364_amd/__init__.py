@@ -21,9 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libarrow.so")
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_IO, ERR_INTERNAL = range(7)
 F32, F16, BF16, F8E4M3 = 0, 1, 2, 3
 LA_RANDOM_FOREST, LA_IDENTITY, LA_SEPARATOR = 0, 1, 2
-KERNEL_CHUNKS, KERNEL_UPPER, KERNEL_LEVEL0, KERNEL_NORM, KERNEL_PERMUTE = range(5)
-KERNEL_NAMES = {KERNEL_CHUNKS: "chunks", KERNEL_UPPER: "upper", KERNEL_LEVEL0: "level0",
-                KERNEL_NORM: "norm", KERNEL_PERMUTE: "permute"}
+KERNEL_CHUNKS, KERNEL_UPPER, KERNEL_LEVEL0, KERNEL_NORM, KERNEL_PERMUTE, KERNEL_COMBINE = range(6)
+KERNEL_NAMES = {KERNEL_CHUNKS: "chunks", KERNEL_UPPER: "upper", KERNEL_COMBINE: "combine",
+                KERNEL_LEVEL0: "level0", KERNEL_NORM: "norm", KERNEL_PERMUTE: "permute"}
 ITER_RENORM = 1
 STATIC_WORKSPACE_BYTES = 64 << 20
 

@@ -99,6 +99,17 @@ struct NormArgs {
 
 hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
                            const TileSet &t, hipStream_t s);
+
+// Rows of the level-0 pass with long lists of partial rows: list j (partial
+// rows idx[ptr[j]] .. idx[ptr[j+1]-1], in order) is summed into partial row
+// out_row0 + j, which the row then lists alone.
+struct CombineArgs {
+    const int32_t *ptr;  // [nrows + 1]
+    const int32_t *idx;
+    int64_t nrows;
+    int64_t out_row0;
+};
+hipError_t launch_combine(int kt, const CombineArgs &a, const TileSet &t, hipStream_t s);
 hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t count, hipStream_t s);
 hipError_t launch_colmax(const float *x, int64_t ldx, int64_t n, int k, unsigned *out,

@@ -110,6 +110,59 @@ __global__ __launch_bounds__(kBlockThreads) void copy_kernel(const vu4 *src, vu4
         dst[i] = src[i];
 }
 
+// Sum of a long list of FP32 partial rows (a hub row of the level-0 pass,
+// which would otherwise add them one batch after another on a single lane
+// group): workgroup (j, tile) splits list j into G contiguous slices, lane
+// group g adds slice g in list order, and the G slice sums are added in
+// slice order.  The order depends on the list and the tile width only.
+template <int KT>
+__global__ __launch_bounds__(kBlockThreads) void combine_kernel(CombineArgs a, TileSet ts) {
+    constexpr int LPR = KT / 4;              // lanes per row, 4 columns (16 bytes) each
+    constexpr int G = kBlockThreads / LPR;   // lane groups
+    const Tile &t = ts.t[blockIdx.x % ts.n];
+    const int64_t j = blockIdx.x / ts.n;
+    if (j >= a.nrows) return;
+    const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+    const int64_t c0 = a.ptr[j], len = a.ptr[j + 1] - c0;
+    const int64_t lo = c0 + len * g / G, hi = c0 + len * (g + 1) / G;
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int64_t c = lo;
+    // four rows in flight at a time, added in list order
+    for (; c + 4 <= hi; c += 4) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            v[u] = *reinterpret_cast<const float4 *>(t.s + (int64_t)a.idx[c + u] * t.lds + sub * 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+            acc.z += v[u].z;
+            acc.w += v[u].w;
+        }
+    }
+    for (; c < hi; ++c) {
+        const float4 v = *reinterpret_cast<const float4 *>(t.s + (int64_t)a.idx[c] * t.lds + sub * 4);
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
+    }
+    __shared__ float4 s_part[G][LPR];
+    s_part[g][sub] = acc;
+    __syncthreads();
+    if (threadIdx.x < LPR) {
+        float4 sum = s_part[0][sub];
+        for (int q = 1; q < G; ++q) {
+            sum.x += s_part[q][sub].x;
+            sum.y += s_part[q][sub].y;
+            sum.z += s_part[q][sub].z;
+            sum.w += s_part[q][sub].w;
+        }
+        *reinterpret_cast<float4 *>(t.s_out + (a.out_row0 + j) * t.lds + sub * 4) = sum;
+    }
+}
+
 }  // namespace dev
 
 ARROW_DECLARE_DT(kF32)
@@ -127,6 +180,19 @@ hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPa
     case kF8E4M3: return row_pass_dt<kF8E4M3>(kt, mode, code16, rp, t, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_combine(int kt, const CombineArgs &a, const TileSet &t, hipStream_t s) {
+    if (a.nrows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(a.nrows * t.n)), block(dev::kBlockThreads);
+    switch (kt) {
+    case 16: hipLaunchKernelGGL(dev::combine_kernel<16>, grid, block, 0, s, a, t); break;
+    case 32: hipLaunchKernelGGL(dev::combine_kernel<32>, grid, block, 0, s, a, t); break;
+    case 64: hipLaunchKernelGGL(dev::combine_kernel<64>, grid, block, 0, s, a, t); break;
+    case 128: hipLaunchKernelGGL(dev::combine_kernel<128>, grid, block, 0, s, a, t); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_norm(const NormArgs &a, int k, hipStream_t s) {

@@ -604,6 +604,35 @@ void plan_build(const Decomp &d, Plan &p, PlanArrays &h) {
             if (!fused[si]) l0_cidx.push_back((int32_t)up_of[si]);
         l0_cptr[r + 1] = (int32_t)l0_cidx.size();
     }
+    // long lists go to the combine pass: such a row lists its combined
+    // partial row alone
+    {
+        auto &hv_ptr = h.hv_ptr, &hv_idx = h.hv_idx;
+        hv_ptr.assign(1, 0);
+        std::vector<int32_t> cptr(n + 1, 0), cidx;
+        cidx.reserve(l0_cidx.size());
+        const int64_t row0 = p.n_up + p.ch_slots;
+        for (int64_t r = 0; r < n; ++r) {
+            const int32_t c0 = l0_cptr[r], c1 = l0_cptr[r + 1];
+            if (c1 - c0 > kCombineList) {
+                cidx.push_back((int32_t)(row0 + (int64_t)hv_ptr.size() - 1));
+                hv_idx.insert(hv_idx.end(), l0_cidx.begin() + c0, l0_cidx.begin() + c1);
+                hv_ptr.push_back((int32_t)hv_idx.size());
+            } else {
+                cidx.insert(cidx.end(), l0_cidx.begin() + c0, l0_cidx.begin() + c1);
+            }
+            cptr[r + 1] = (int32_t)cidx.size();
+        }
+        p.n_heavy = (int64_t)hv_ptr.size() - 1;
+        p.hv_nlist = (int64_t)hv_idx.size();
+        p.s_rows += p.n_heavy;
+        if (p.n_heavy == 0) {
+            hv_ptr.clear();
+        } else {
+            l0_cptr.swap(cptr);
+            l0_cidx.swap(cidx);
+        }
+    }
     p.l0_batch = p.l0_batch_auto = choose_batch<int32_t>(n, l0_ptr.data(), l0_cptr.data());
     p.up_batch = p.up_batch_auto =
         choose_batch<int32_t>(p.n_up, up_ptr.data(), up_cptr.data());
@@ -711,6 +740,10 @@ arrow_status_t plan_create(const Decomp &d, int device, hipStream_t stream, Plan
     UP(p.ch_col, h.ch_col);
     UP(p.ch_val, h.ch_val);
     UP(p.vop0, L0.vop);
+    if (p.n_heavy > 0) {
+        UP(p.hv_ptr, h.hv_ptr);
+        UP(p.hv_idx, h.hv_idx);
+    }
 #undef UP
     if (st == ARROW_OK) {
         e = hipStreamSynchronize(stream);
@@ -890,6 +923,11 @@ arrow_status_t spmm_group(Plan &p, const OpState *ops, int nops, void *const *ws
             ProfScope ps(p, ARROW_KERNEL_UPPER, s);
             LAUNCH_OK(launch_row_pass(kt, dtype, kPassUpper, false, upp, ts, s));
         }
+        if (p.n_heavy > 0) {
+            ProfScope ps(p, ARROW_KERNEL_COMBINE, s);
+            CombineArgs ca{p.hv_ptr, p.hv_idx, p.n_heavy, p.n_up + p.ch_slots};
+            LAUNCH_OK(launch_combine(kt, ca, ts, s));
+        }
         {
             ProfScope ps(p, ARROW_KERNEL_LEVEL0, s);
             LAUNCH_OK(launch_row_pass(kt, dtype, kPassLevel0, p.code16, l0, ts, s));
@@ -946,6 +984,9 @@ int64_t kernel_bytes(const Plan &p, int kernel, int64_t k, int dtype) {
         return nb * k * (8 + (scaled ? 4 : 0)) + k * 16;
     case ARROW_KERNEL_PERMUTE:
         return p.n * 4 + p.n * k * (4 + sx);
+    case ARROW_KERNEL_COMBINE:
+        if (p.n_heavy == 0) return 0;
+        return (p.n_heavy + 1) * 4 + p.hv_nlist * (4 + k * 4) + p.n_heavy * k * 4;
     default:
         return -1;
     }

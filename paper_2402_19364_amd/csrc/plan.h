@@ -30,6 +30,13 @@ static_assert(kChunkWindows % kXcds == 0, "chunk windows");
 #define ARROW_WINDOW_ROW 256
 #endif
 constexpr int kWindowRow = ARROW_WINDOW_ROW;
+// Level-0 rows listing more partial rows than this have them summed by the
+// combine pass first (a hub row's chunks, added in parallel instead of one
+// batch after another by one lane group).
+#ifndef ARROW_COMBINE_LIST
+#define ARROW_COMBINE_LIST 32
+#endif
+constexpr int kCombineList = ARROW_COMBINE_LIST;
 
 struct ProfRec {
     int kernel;
@@ -90,7 +97,12 @@ struct Plan {
     int32_t up_batch = kBatchWide, l0_batch = kBatchWide;
     int32_t up_batch_auto = kBatchWide, l0_batch_auto = kBatchWide;
 
-    int64_t s_rows = 0;  // partial-row buffer rows = n_up + ch_slots
+    // level-0 rows with more than kCombineList listed partial rows: list j is
+    // summed by the combine pass into partial row n_up + ch_slots + j
+    int64_t n_heavy = 0, hv_nlist = 0;
+    int32_t *hv_ptr = nullptr, *hv_idx = nullptr;
+
+    int64_t s_rows = 0;  // partial-row buffer rows = n_up + ch_slots + n_heavy
     // distinct X rows each pass reads (algorithmic byte model)
     int64_t distinct_l0 = 0, distinct_up = 0, distinct_ch = 0;
 
@@ -112,6 +124,7 @@ struct PlanArrays {
     std::vector<float> up_val;
     std::vector<int32_t> ch_ptr, ch_col;
     std::vector<float> ch_val;
+    std::vector<int32_t> hv_ptr, hv_idx;
 };
 // Builds the plan's host arrays and fills the scalar fields of `p` (no
 // device work).

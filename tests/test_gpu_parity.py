@@ -117,6 +117,27 @@ def test_strided_rows_and_hubs():
     _check_trajectory(M, 16, 32, 3, ld=48, label="hubs ld=48")
 
 
+@pytest.mark.parametrize("k", [16, 32, 64, 128])
+def test_long_partial_row_lists_are_combined(k):
+    # a hub row cut into about 150 chunks lists all of their partial rows:
+    # the combine pass sums them before the level-0 pass (every tile width of
+    # its kernel; the scaled formats meet it in the full-size R-MAT tests)
+    n = 10000
+    rng = np.random.default_rng(8)
+    edges = [(0, i) for i in range(1, n)]
+    edges += [(int(a), int(b)) for a, b in rng.integers(0, n, (30000, 2)) if a != b]
+    M = W.from_edges(n, edges, values="uniform", seed=9, diagonal=True)
+    plan = _check_trajectory(M, 16, k, 3, label=f"combined lists k={k}")
+    assert plan.kernel_bytes(A_.KERNEL_COMBINE, k) > 0
+    plan.profile(True)
+    x = plan.empty(k)
+    x.copy_(torch.from_numpy(W.features(M.n, k, 1)).cuda())
+    run_steps(plan, x, 1, torch)
+    torch.cuda.synchronize()
+    assert plan.profile_query(A_.KERNEL_COMBINE)[0] >= 1
+    plan.profile(False)
+
+
 def test_gather_batches_agree():
     # rows longer than every short batch and rows listing more than 2 partial
     # rows: each batch must give the same products (the schedule changes, the
