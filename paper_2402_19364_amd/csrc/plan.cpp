@@ -604,8 +604,8 @@ void plan_build(const Decomp &d, Plan &p, PlanArrays &h) {
             if (!fused[si]) l0_cidx.push_back((int32_t)up_of[si]);
         l0_cptr[r + 1] = (int32_t)l0_cidx.size();
     }
-    // long lists go to the combine pass: such a row lists its combined
-    // partial row alone
+    // long lists go to the combine pass, in units of at most kCombineUnit
+    // partial rows: such a row lists its units' sums
     {
         auto &hv_ptr = h.hv_ptr, &hv_idx = h.hv_idx;
         hv_ptr.assign(1, 0);
@@ -614,10 +614,15 @@ void plan_build(const Decomp &d, Plan &p, PlanArrays &h) {
         const int64_t row0 = p.n_up + p.ch_slots;
         for (int64_t r = 0; r < n; ++r) {
             const int32_t c0 = l0_cptr[r], c1 = l0_cptr[r + 1];
-            if (c1 - c0 > kCombineList) {
-                cidx.push_back((int32_t)(row0 + (int64_t)hv_ptr.size() - 1));
-                hv_idx.insert(hv_idx.end(), l0_cidx.begin() + c0, l0_cidx.begin() + c1);
-                hv_ptr.push_back((int32_t)hv_idx.size());
+            const int64_t len = c1 - c0;
+            if (len > kCombineList) {
+                const int64_t nu = (len + kCombineUnit - 1) / kCombineUnit;
+                for (int64_t u = 0; u < nu; ++u) {
+                    cidx.push_back((int32_t)(row0 + (int64_t)hv_ptr.size() - 1));
+                    hv_idx.insert(hv_idx.end(), l0_cidx.begin() + c0 + len * u / nu,
+                                  l0_cidx.begin() + c0 + len * (u + 1) / nu);
+                    hv_ptr.push_back((int32_t)hv_idx.size());
+                }
             } else {
                 cidx.insert(cidx.end(), l0_cidx.begin() + c0, l0_cidx.begin() + c1);
             }

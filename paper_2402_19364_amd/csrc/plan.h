@@ -37,6 +37,13 @@ constexpr int kWindowRow = ARROW_WINDOW_ROW;
 #define ARROW_COMBINE_LIST 32
 #endif
 constexpr int kCombineList = ARROW_COMBINE_LIST;
+// A long list is cut into units of at most this many partial rows (equal
+// shares), each summed by its own workgroup into one partial row; the row
+// then lists its units' sums in order.
+#ifndef ARROW_COMBINE_UNIT
+#define ARROW_COMBINE_UNIT 64
+#endif
+constexpr int kCombineUnit = ARROW_COMBINE_UNIT;
 
 struct ProfRec {
     int kernel;
@@ -97,9 +104,10 @@ struct Plan {
     int32_t up_batch = kBatchWide, l0_batch = kBatchWide;
     int32_t up_batch_auto = kBatchWide, l0_batch_auto = kBatchWide;
 
-    // level-0 rows with more than kCombineList listed partial rows: list j is
-    // summed by the combine pass into partial row n_up + ch_slots + j
-    int64_t n_heavy = 0, hv_nlist = 0;
+    // level-0 rows with more than kCombineList listed partial rows: their
+    // lists cut into units, unit j summed by the combine pass into partial
+    // row n_up + ch_slots + j
+    int64_t n_heavy = 0, hv_nlist = 0;  // units, partial rows they sum
     int32_t *hv_ptr = nullptr, *hv_idx = nullptr;
 
     int64_t s_rows = 0;  // partial-row buffer rows = n_up + ch_slots + n_heavy
