@@ -100,9 +100,9 @@ struct NormArgs {
 hipError_t launch_row_pass(int kt, int dtype, int mode, bool code16, const RowPass &rp,
                            const TileSet &t, hipStream_t s);
 
-// Rows of the level-0 pass with long lists of partial rows: list j (partial
-// rows idx[ptr[j]] .. idx[ptr[j+1]-1], in order) is summed into partial row
-// out_row0 + j, which the row then lists alone.
+// Rows of the level-0 pass with long lists of partial rows: their lists cut
+// into units; unit j (partial rows idx[ptr[j]] .. idx[ptr[j+1]-1], in order)
+// is summed into partial row out_row0 + j, and the row lists its units' sums.
 struct CombineArgs {
     const int32_t *ptr;  // [nrows + 1]
     const int32_t *idx;

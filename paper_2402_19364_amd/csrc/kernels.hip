@@ -110,11 +110,12 @@ __global__ __launch_bounds__(kBlockThreads) void copy_kernel(const vu4 *src, vu4
         dst[i] = src[i];
 }
 
-// Sum of a long list of FP32 partial rows (a hub row of the level-0 pass,
-// which would otherwise add them one batch after another on a single lane
-// group): workgroup (j, tile) splits list j into G contiguous slices, lane
-// group g adds slice g in list order, and the G slice sums are added in
-// slice order.  The order depends on the list and the tile width only.
+// Sum of one unit of a long list of FP32 partial rows (a hub row of the
+// level-0 pass, which would otherwise add them one batch after another on a
+// single lane group): workgroup (j, tile) splits unit j into G contiguous
+// slices, lane group g adds slice g in list order, and the G slice sums are
+// added in slice order.  The order depends on the unit and the tile width
+// only.
 template <int KT>
 __global__ __launch_bounds__(kBlockThreads) void combine_kernel(CombineArgs a, TileSet ts) {
     constexpr int LPR = KT / 4;              // lanes per row, 4 columns (16 bytes) each
